@@ -1,0 +1,207 @@
+"""Benchmark: whole-solve throughput of the viscoelastic FDTD hot path on one GPU.
+
+A step is one pass of the hot path over the workload: Rayleigh source plane,
+full time loop (velocity, stress + memory variables, absorbing layer, soft
+source, peak capture) and the peak-voxel reduction, with the plan (material
+tables, time step, layer profile) built once beforehand and the inputs already
+resident in HBM.  Default workload: 400x400x520 skull at 700 kHz, PPW 9, 5000
+time steps.
+
+Prints one JSON line: Gcell-updates/s, the dominant kernel's roofline (its
+algorithmic bytes over its HIP-event-timed average launch), and the FP64 oracle
+timed on the host cores over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_12727_amd", "csrc", f)
+                  for f in ("fdtd.hip", "bbfd_dev.h")]
+
+WORKLOADS = {
+    "skull400": lambda: __import__("synth").skull400(),
+    "skull200": lambda: __import__("synth").skull200(),
+    "plate64": lambda: __import__("synth").plate_case(),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def slab_cells(case) -> list:
+    """Cells inside the absorbing layer of each axis (x, y, z slabs)."""
+    L = case.pml
+    n = (case.nx, case.ny, case.nz)
+    out = []
+    for a in range(3):
+        others = 1
+        for b in range(3):
+            if b != a:
+                others *= n[b]
+        out.append(2 * L * others)
+    return out
+
+
+def algorithmic_bytes(case, info) -> dict:
+    """Bytes each kernel must move per launch at perfect on-chip reuse (FP32
+    state, 1-byte index), averaged over the time loop.
+      velocity: read 6 stresses + 3 velocities + index, write 3 velocities
+                = 49 B/cell, + 3 layer memories read+write (24 B) per slab cell
+      stress:   read 3 velocities + 6 stresses + 6 memories + index, write 6 +
+                6 = 109 B/cell, + 3 layer memories (24 B) per slab cell,
+                + 8 B/cell (peak read+write) in capture steps, + source plane."""
+    cells = case.cells
+    slabs = sum(slab_cells(case))
+    steps = case.n_steps
+    cap_steps = steps - info["capture_start"]
+    vel = 49 * cells + 24 * slabs
+    stress = 109 * cells + 24 * slabs + 8 * cells * cap_steps / steps + 8 * case.nx * case.ny
+    return {"velocity": vel, "stress": stress, "per_cell_update": (vel + stress) / cells}
+
+
+def load_traffic(kernel: str, workload: str):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by
+    a copy kernel's counters), valid only for the kernel sources it was taken on."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash() or t.get("workload") != workload:
+        return None
+    return t.get("kernels", {}).get(kernel)
+
+
+def cpu_baseline(case, sample_steps: int = 2) -> dict:
+    """FP64 oracle on the host cores: full workload grid, one untimed step
+    (first touch), then ``sample_steps`` timed steps."""
+    import numpy as np
+    import oracle
+    prob = oracle.problem_from_case(case)
+    src = oracle.source_plane(case)
+    sim = oracle.Sim(prob, case.mat)
+    sim.step(0, src)
+    t0 = time.perf_counter()
+    for n in range(1, 1 + sample_steps):
+        sim.step(n, src)
+    dt = time.perf_counter() - t0
+    sim.close()
+    del np
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": case.cells * sample_steps / dt / 1e9, "unit": "Gcell-updates/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"{case.name}: full grid, {sample_steps} time steps after one untimed "
+                      f"step ({dt:.1f} s, FP64, OpenMP)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="skull400", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2301_12727_amd as bb
+
+    case = WORKLOADS[args.workload]()
+    log(f"[bench] workload {case.name}: {case.nx}x{case.ny}x{case.nz}, {case.n_steps} steps")
+    plan = bb.Plan.from_case(case)
+    info = plan.info
+    dev = torch.device("cuda:0")
+    ws = plan.workspace(dev)
+    mat = torch.from_numpy(case.mat).to(dev)
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=dev)
+    peak = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+
+    def step():
+        plan.source_rayleigh(case.transducer, src, ws)
+        plan.solve(mat, src, peak, ws)
+
+    for w in range(args.warmup):
+        step()
+        plan.status(ws)
+        log(f"[bench] warmup {w} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pidx, pval = plan.status(ws)
+    log(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; peak voxel {pidx} ({pval:.4e} Pa)")
+    updates = case.cells * case.n_steps
+    value = args.steps * updates / elapsed / 1e9
+
+    # dominant kernel: per-launch HIP events on the launch stream
+    ms_v, ms_s = plan.solve_profiled(mat, src, peak, ws)
+    pidx2, _ = plan.status(ws)
+    assert pidx2 == pidx
+    ab = algorithmic_bytes(case, info)
+    avg = {"velocity": ms_v / case.n_steps, "stress": ms_s / case.n_steps}
+    dom = "stress" if avg["stress"] >= avg["velocity"] else "velocity"
+    achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
+    log(f"[bench] kernel avg ms: velocity {avg['velocity']:.4f} stress {avg['stress']:.4f}")
+    traffic = load_traffic(dom, case.name)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"k_{dom}", "avg_launch_ms": round(avg[dom], 5),
+            "algorithmic_bytes_per_launch": int(ab[dom]),
+            "bytes_per_cell_update": round(ab["per_cell_update"], 2)}
+
+    out = {
+        "metric": "Gcell-updates/s",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "grid": [case.nx, case.ny, case.nz],
+                   "time_steps": case.n_steps, "freq_hz": case.freq_hz, "ppw": case.ppw,
+                   "pml": case.pml, "materials": int(case.materials.shape[0])},
+        "effective_hbm_gbs": round(value * ab["per_cell_update"], 1),
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,156 @@
+/*
+ * bbfd -- MI355X (gfx950) viscoelastic FDTD for transcranial ultrasound.
+ *
+ * C ABI of the hot path of BabelBrain's acoustic step (arXiv 2301.12727,
+ * Section 2.3): a material map plus property table, a transducer, a frequency
+ * and points-per-wavelength in; the transmitted peak-pressure map out.
+ *
+ * Conventions
+ *  - SI units.  3D arrays are C-order [nz][ny][nx] (x fastest), z is the
+ *    acoustic axis; cell (i, j, k) has its centre at (i dx, j dx, k dx).
+ *  - "dev" marks a device pointer.  The caller allocates and owns every device
+ *    buffer, including the workspace (size from bbfd_plan_get_info); the library
+ *    allocates no device memory.  Plans own only host data and, once a solve
+ *    has been captured, a HIP graph.
+ *  - "stream" is a hipStream_t (NULL = legacy default stream).  Device work is
+ *    enqueued asynchronously unless stated otherwise.
+ *  - Every call returns BBFD_OK (0) or a negative code; no C++ exception
+ *    crosses the ABI.  bbfd_last_error() describes the last failure of the
+ *    calling thread.
+ *  - A plan is immutable once created and may be shared across threads; two
+ *    solves in flight at the same time need distinct workspaces.
+ */
+#ifndef BBFD_H
+#define BBFD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BBFD_OK 0
+#define BBFD_EINVAL (-1)    /* bad size, pointer, step count, layer thickness */
+#define BBFD_EMATERIAL (-2) /* rho <= 0, Q <= 1, Poisson ratio outside [-1, 0.5) */
+#define BBFD_EINDEX (-3)    /* device found a material index >= n_materials */
+#define BBFD_EGEOMETRY (-4) /* source plane inside the layer; element at/after it */
+#define BBFD_EDIVERGED (-5) /* non-finite value in the peak map */
+#define BBFD_EHIP (-6)      /* HIP runtime error */
+#define BBFD_ENOMEM (-7)    /* workspace missing or too small */
+
+/* One row of the property table (paper Section 2.2.1, Table 1): density,
+   longitudinal and shear speed, longitudinal and shear attenuation in Np/m at
+   the drive frequency.  c_s = 0 marks a fluid. */
+typedef struct {
+  double rho, c_l, c_s, alpha_l, alpha_s;
+} bbfd_material;
+
+/* Problem statement (Sections 2.2-2.3 and 3.2).
+   dx = 1500 / (freq_hz * ppw) (Section 2.2, PPW in water).
+   qc: attenuation correction, Q = Q0 * qc (Section 3.2; 1 = none).
+   cfl_safety: fraction of the 3D stability limit used to size dt (0.95).
+   pml: absorbing-layer thickness in cells on every face (8 by default).
+   capture_start: first step whose end state enters the peak map
+                  (< 0: n_steps - 2 periods).
+   source_k: plane of the soft stress source (< 0: pml, the first interior
+             plane).  The property table is copied at plan creation. */
+typedef struct {
+  int32_t nx, ny, nz, pml;
+  double freq_hz, ppw, qc, cfl_safety;
+  int32_t n_steps, capture_start, source_k;
+  int32_t n_materials; /* 1..256 */
+  const bbfd_material *materials;
+} bbfd_problem;
+
+/* Single-element transducer (Section 2, "Single").  kind 0: flat piston,
+   radius_m = face radius, apex_m = face centre.  kind 1: spherical bowl,
+   radius_m = aperture radius, focal_m = radius of curvature, apex_m = apex on
+   the axis.  axis: propagation direction (normalised by the library).
+   u0: normal surface velocity amplitude (m/s). */
+typedef struct {
+  int32_t kind;
+  double radius_m, focal_m, apex_m[3], axis[3], u0;
+} bbfd_transducer;
+
+typedef struct {
+  double dx, dt, c_max;       /* grid spacing, time step, fastest unrelaxed speed */
+  int32_t steps_per_period;   /* dt = period / steps_per_period */
+  int32_t capture_start, source_k, pitch;
+  uint64_t workspace_bytes;   /* device workspace a solve needs */
+  uint64_t cells;             /* nx * ny * nz */
+} bbfd_plan_info;
+
+typedef struct bbfd_plan bbfd_plan;
+
+/* Validates the problem and derives, in FP64 on the host, the per-material
+   Zener constants (Q from Eq. 3 times qc, one relaxation mechanism at the drive
+   frequency), the time step and the absorbing-layer profile; packs them as the
+   FP32 device tables.  *out is NULL on failure. */
+int bbfd_plan_create(const bbfd_problem *problem, bbfd_plan **out);
+int bbfd_plan_get_info(const bbfd_plan *plan, bbfd_plan_info *out);
+void bbfd_plan_destroy(bbfd_plan *plan);
+
+/* Host copy of the FP64 per-material constants: n_materials rows of
+   (Q_P, Q_S, tau_P, tau_S, pi_R, mu_R, pi_U, mu_U, nu). */
+int bbfd_material_constants(const bbfd_plan *plan, double *out, int32_t n_rows);
+
+/* Surface decomposition of the transducer (Section 2.3: elements of area
+   lambda^2/16): rings no wider than lambda/4, each split into the fewest
+   equal elements no larger than lambda^2/16.  Writes up to cap rows of
+   (x, y, z, area) to host memory xyza (may be NULL to count); *n_out gets the
+   element count. */
+int bbfd_transducer_elements(const bbfd_plan *plan, const bbfd_transducer *t, double *xyza,
+                             int64_t cap, int64_t *n_out);
+
+/* Rayleigh-Sommerfeld field of the transducer radiating into water (Section
+   2.3) at the cell centres of the source plane:
+     S(x) = (i omega rho_w / 2 pi) sum_e u0 A_e exp(-i k R_e) / R_e
+   (e^{+i omega t}); src_re_im (dev) receives 2*nx*ny floats, (re, im)
+   interleaved, [ny][nx].  Uses the front of the workspace to stage the
+   elements and blocks until they are uploaded.  BBFD_EGEOMETRY if an element
+   lies at or beyond the source plane. */
+int bbfd_source_rayleigh(const bbfd_plan *plan, const bbfd_transducer *t, float *src_re_im,
+                         void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Full FDTD solve (Eq. 1 with memory variables, absorbing layer, soft source,
+   peak capture), enqueued on stream:
+     mat (dev)        uint8 [nz][ny][nx] material indices into the table
+     src_re_im (dev)  complex source plane as written by bbfd_source_rayleigh
+     peak (dev)       float [nz][ny][nx], receives max |p| over the capture
+                      window, p = -(sxx + syy + szz)/3
+     workspace (dev)  >= workspace_bytes, 256-byte aligned; no need to clear
+   The first solve with a given (mat, src, peak, workspace) captures the time
+   loop into a HIP graph owned by the plan; later solves with the same
+   pointers replay it.  Index and divergence errors are detected on the device
+   and reported by bbfd_status. */
+int bbfd_solve(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im, float *peak,
+               void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Same as bbfd_solve but launches kernels directly (no graph). */
+int bbfd_solve_direct(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
+                      float *peak, void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Profiling variant of bbfd_solve_direct: records a HIP event before and after
+   every kernel of the time loop on stream, waits for the solve, and writes the
+   summed kernel times in milliseconds: ms_out[0] = velocity update (Eq. 1 rows
+   1-3), ms_out[1] = stress/memory update (rows 4-9).  Results are identical to
+   bbfd_solve. */
+int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
+                        float *peak, void *workspace, uint64_t workspace_bytes, void *stream,
+                        double *ms_out);
+
+/* Waits for stream, then reads the device status of the last solve in this
+   workspace: BBFD_EINDEX, BBFD_EDIVERGED or BBFD_OK.  peak_index receives the
+   linear index (x fastest) of the largest peak value over the interior outside
+   the absorbing layer (lowest index on ties), peak_value that value.  Either
+   output may be NULL. */
+int bbfd_status(const bbfd_plan *plan, const void *workspace, int64_t *peak_index,
+                float *peak_value, void *stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *bbfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

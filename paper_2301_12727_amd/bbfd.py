@@ -1,0 +1,211 @@
+"""ctypes binding of libbbfd (include/bbfd.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; this module passes device
+pointers (torch tensors' ``data_ptr()``) and HIP stream handles through.  It
+raises if the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbfd.so")
+
+OK, EINVAL, EMATERIAL, EINDEX, EGEOMETRY, EDIVERGED, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+ERROR_NAMES = {EINVAL: "EINVAL", EMATERIAL: "EMATERIAL", EINDEX: "EINDEX",
+               EGEOMETRY: "EGEOMETRY", EDIVERGED: "EDIVERGED", EHIP: "EHIP", ENOMEM: "ENOMEM"}
+
+
+class BBFDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("rho", C.c_double), ("c_l", C.c_double), ("c_s", C.c_double),
+                ("alpha_l", C.c_double), ("alpha_s", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pml", C.c_int32),
+                ("freq_hz", C.c_double), ("ppw", C.c_double), ("qc", C.c_double),
+                ("cfl_safety", C.c_double),
+                ("n_steps", C.c_int32), ("capture_start", C.c_int32), ("source_k", C.c_int32),
+                ("n_materials", C.c_int32), ("materials", C.POINTER(Material))]
+
+
+class Transducer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("radius_m", C.c_double), ("focal_m", C.c_double),
+                ("apex_m", C.c_double * 3), ("axis", C.c_double * 3), ("u0", C.c_double)]
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("dx", C.c_double), ("dt", C.c_double), ("c_max", C.c_double),
+                ("steps_per_period", C.c_int32), ("capture_start", C.c_int32),
+                ("source_k", C.c_int32), ("pitch", C.c_int32),
+                ("workspace_bytes", C.c_uint64), ("cells", C.c_uint64)]
+
+
+EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
+           "bbfd_material_constants", "bbfd_transducer_elements", "bbfd_source_rayleigh",
+           "bbfd_solve", "bbfd_solve_direct", "bbfd_solve_profiled", "bbfd_status",
+           "bbfd_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libbbfd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.bbfd_plan_create.argtypes = [C.POINTER(Problem), C.POINTER(vp)]
+        L.bbfd_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
+        L.bbfd_plan_destroy.argtypes = [vp]
+        L.bbfd_plan_destroy.restype = None
+        L.bbfd_material_constants.argtypes = [vp, vp, C.c_int32]
+        L.bbfd_transducer_elements.argtypes = [vp, C.POINTER(Transducer), vp, C.c_int64,
+                                               C.POINTER(C.c_int64)]
+        L.bbfd_source_rayleigh.argtypes = [vp, C.POINTER(Transducer), vp, vp, C.c_uint64, vp]
+        L.bbfd_solve.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
+        L.bbfd_solve_direct.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
+        L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
+        L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
+        L.bbfd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise BBFDError(rc, lib().bbfd_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def transducer_struct(t) -> Transducer:
+    return Transducer(int(t.kind), float(t.radius), float(t.focal), (C.c_double * 3)(*t.apex),
+                      (C.c_double * 3)(*t.axis), float(t.u0))
+
+
+class Plan:
+    """A validated problem with its derived device tables (libbbfd plan)."""
+
+    def __init__(self, nx, ny, nz, freq_hz, ppw, n_steps, materials, pml=8, qc=1.0,
+                 cfl_safety=0.95, capture_start=-1, source_k=-1):
+        mats = np.ascontiguousarray(materials, dtype=np.float64).reshape(-1, 5)
+        self._mats = (Material * len(mats))(*[Material(*map(float, r)) for r in mats])
+        self.problem = Problem(nx, ny, nz, pml, freq_hz, ppw, qc, cfl_safety, n_steps,
+                               capture_start, source_k, len(mats), self._mats)
+        self.h = C.c_void_p()
+        _check(lib().bbfd_plan_create(C.byref(self.problem), C.byref(self.h)))
+        info = PlanInfo()
+        _check(lib().bbfd_plan_get_info(self.h, C.byref(info)))
+        self.info = {n: getattr(info, n) for n, _ in PlanInfo._fields_}
+        self.shape = (nz, ny, nx)
+        self.n_materials = len(mats)
+
+    @classmethod
+    def from_case(cls, case, n_steps=None, **over):
+        kw = dict(nx=case.nx, ny=case.ny, nz=case.nz, freq_hz=case.freq_hz, ppw=case.ppw,
+                  n_steps=case.n_steps if n_steps is None else n_steps,
+                  materials=case.materials, pml=case.pml, qc=case.qc,
+                  cfl_safety=case.cfl_safety, capture_start=case.capture_start,
+                  source_k=case.source_k)
+        kw.update(over)
+        return cls(**kw)
+
+    def close(self):
+        if self.h:
+            lib().bbfd_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.info["workspace_bytes"])
+
+    def material_constants(self) -> np.ndarray:
+        out = np.empty((self.n_materials, 9), dtype=np.float64)
+        _check(lib().bbfd_material_constants(self.h, out.ctypes.data_as(C.c_void_p),
+                                             self.n_materials))
+        return out
+
+    def elements(self, t) -> np.ndarray:
+        ts = transducer_struct(t)
+        n = C.c_int64(0)
+        _check(lib().bbfd_transducer_elements(self.h, C.byref(ts), None, 0, C.byref(n)))
+        out = np.empty((n.value, 4), dtype=np.float64)
+        _check(lib().bbfd_transducer_elements(self.h, C.byref(ts), out.ctypes.data_as(C.c_void_p),
+                                              n.value, C.byref(n)))
+        return out
+
+    # --------------------------------------------------------- device calls
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def source_rayleigh(self, t, src, ws, stream=None):
+        """Fill ``src`` (torch complex64 or float32 [ny, nx, 2], device) with the
+        Rayleigh field on the source plane."""
+        ts = transducer_struct(t)
+        _check(lib().bbfd_source_rayleigh(self.h, C.byref(ts), C.c_void_p(src.data_ptr()),
+                                          C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                          C.c_void_p(_stream(stream))))
+
+    def solve(self, mat, src, peak, ws, stream=None, graph=True):
+        """Enqueue a full solve (asynchronous)."""
+        fn = lib().bbfd_solve if graph else lib().bbfd_solve_direct
+        _check(fn(self.h, C.c_void_p(mat.data_ptr()), C.c_void_p(src.data_ptr()),
+                  C.c_void_p(peak.data_ptr()), C.c_void_p(ws.data_ptr()),
+                  ws.numel() * ws.element_size(), C.c_void_p(_stream(stream))))
+
+    def solve_profiled(self, mat, src, peak, ws, stream=None):
+        """Direct-launch solve with per-kernel HIP events on the launch stream;
+        returns (velocity ms, stress ms) summed over the time loop."""
+        out = np.zeros(2, dtype=np.float64)
+        _check(lib().bbfd_solve_profiled(self.h, C.c_void_p(mat.data_ptr()),
+                                         C.c_void_p(src.data_ptr()), C.c_void_p(peak.data_ptr()),
+                                         C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                         C.c_void_p(_stream(stream)),
+                                         out.ctypes.data_as(C.c_void_p)))
+        return float(out[0]), float(out[1])
+
+    def status(self, ws, stream=None):
+        """Synchronise and return (peak_index, peak_value); raises on device errors."""
+        idx = C.c_int64(-1)
+        val = C.c_float(0.0)
+        _check(lib().bbfd_status(self.h, C.c_void_p(ws.data_ptr()), C.byref(idx), C.byref(val),
+                                 C.c_void_p(_stream(stream))))
+        return int(idx.value), float(val.value)
+
+
+def run_case(case, n_steps=None, device="cuda", graph=True, **over):
+    """Rayleigh source + full solve of a synthetic case on the GPU.
+    Returns (peak torch.float32 [nz, ny, nx], peak_index, peak_value, plan)."""
+    import torch
+    plan = Plan.from_case(case, n_steps=n_steps, **over)
+    ws = plan.workspace(device)
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=device)
+    plan.source_rayleigh(case.transducer, src, ws)
+    mat = torch.from_numpy(np.ascontiguousarray(case.mat)).to(device)
+    peak = torch.empty(plan.shape, dtype=torch.float32, device=device)
+    plan.solve(mat, src, peak, ws, graph=graph)
+    idx, val = plan.status(ws)
+    return peak, idx, val, plan

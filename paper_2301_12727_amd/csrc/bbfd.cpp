@@ -1,0 +1,616 @@
+// Host side of libbbfd: problem validation, FP64 derivation of the material,
+// time-step and absorbing-layer constants, workspace layout, graph capture of
+// the time loop and the C ABI declared in include/bbfd.h.
+#include "bbfd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bbfd_dev.h"
+
+namespace bbfd {
+hipError_t launch_step(const StepArgs &a, hipStream_t s);
+hipError_t launch_velocity(const StepArgs &a, hipStream_t s);
+hipError_t launch_stress(const StepArgs &a, hipStream_t s);
+hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
+                       hipStream_t s);
+hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
+hipError_t launch_argmax(const float *P, int nx, int ny, int nz, int L, float *pv, long long *pi,
+                         Status *st, hipStream_t s);
+int argmax_partials();
+hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, double dx, double z,
+                           double kw, double pre, float2 *out, hipStream_t s);
+}  // namespace bbfd
+
+using namespace bbfd;
+
+namespace {
+
+constexpr double kCw = 1500.0;   // water speed (Table 1), also fixes dx from PPW
+constexpr double kRhoW = 1000.0; // water density (Table 1)
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC1 = 9.0 / 8.0, kC2 = -1.0 / 24.0;
+constexpr double kPmlR0 = 1e-3;  // design reflection of the absorbing layer
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(BBFD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Zener element relaxing at omega0 with strength tau: factor applied to rho c^2
+// so that the phase speed at omega0 equals the tabulated speed.
+double relaxed_factor(double tau) {
+  const std::complex<double> m = std::complex<double>(1.0, 1.0 + tau) / std::complex<double>(1.0, 1.0);
+  const double re = std::real(1.0 / std::sqrt(m));
+  return re * re;
+}
+
+}  // namespace
+
+struct bbfd_plan {
+  bbfd_problem prob{};
+  std::vector<bbfd_material> mats;
+  double dx = 0, dt = 0, omega = 0, cmax = 0, d0 = 0;
+  int nt = 0, cap = 0, ks = 0;
+  std::vector<double> consts;  // 9 per material
+  Grid g{};
+  std::vector<float> lut;      // n_materials x kLutW
+  std::vector<float4> pmltab;  // nx + ny + nz entries
+  float *h_lut = nullptr;      // pinned copies, made at the first solve
+  float4 *h_pml = nullptr;
+  float relax_a = 0, relax_b = 0;
+  std::vector<float> src_c, src_s;
+  int kchunk = 1;
+  size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
+         off_state = 0, off_psi = 0, ws_bytes = 0;
+  std::mutex mu;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *key[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+int validate_and_derive(const bbfd_problem *p, bbfd_plan *pl) {
+  if (!p) return fail(BBFD_EINVAL, "null problem");
+  if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->pml < 0 || p->n_steps <= 0)
+    return fail(BBFD_EINVAL, "sizes must be positive (nx %d ny %d nz %d pml %d steps %d)", p->nx,
+                p->ny, p->nz, p->pml, p->n_steps);
+  if (2 * p->pml >= p->nx || 2 * p->pml >= p->ny || 2 * p->pml >= p->nz)
+    return fail(BBFD_EINVAL, "absorbing layer of %d cells does not fit the grid", p->pml);
+  if ((long long)p->nx * p->ny > (1LL << 30))
+    return fail(BBFD_EINVAL, "plane too large");
+  if (!(p->freq_hz > 0) || !(p->ppw > 0) || !(p->qc > 0) || !(p->cfl_safety > 0))
+    return fail(BBFD_EINVAL, "frequency, ppw, qc and cfl_safety must be positive");
+  if (p->n_materials < 1 || p->n_materials > 256 || !p->materials)
+    return fail(BBFD_EINVAL, "need 1..256 materials");
+  pl->prob = *p;
+  pl->mats.assign(p->materials, p->materials + p->n_materials);
+  pl->prob.materials = pl->mats.data();
+
+  const double dx = kCw / (p->freq_hz * p->ppw);  // PPW counted in water
+  const double w0 = 2.0 * kPi * p->freq_hz;
+  const double T = 1.0 / p->freq_hz;
+  double cmax = 0.0;
+  pl->consts.assign(9 * (size_t)p->n_materials, 0.0);
+  for (int m = 0; m < p->n_materials; ++m) {
+    const bbfd_material &q = pl->mats[m];
+    if (!(q.rho > 0) || !(q.c_l > 0) || !(q.c_s >= 0) || !(q.alpha_l >= 0) || !(q.alpha_s >= 0))
+      return fail(BBFD_EMATERIAL, "material %d: non-positive density/speed or negative attenuation", m);
+    double nu = 0.5;  // fluid
+    if (q.c_s > 0) {
+      const double l2 = q.c_l * q.c_l, s2 = q.c_s * q.c_s;
+      if (!(l2 > s2)) return fail(BBFD_EMATERIAL, "material %d: shear speed >= longitudinal", m);
+      nu = (l2 - 2.0 * s2) / (2.0 * (l2 - s2));
+      if (nu < -1.0 || nu >= 0.5)
+        return fail(BBFD_EMATERIAL, "material %d: Poisson ratio %g outside [-1, 0.5)", m, nu);
+    }
+    // Q = qc * omega / (2 c alpha) (Eq. 3 with the correction factor); no loss -> Q infinite.
+    const double qp = q.alpha_l > 0 ? p->qc * w0 / (2.0 * q.c_l * q.alpha_l) : HUGE_VAL;
+    const double qs = (q.c_s > 0 && q.alpha_s > 0) ? p->qc * w0 / (2.0 * q.c_s * q.alpha_s) : HUGE_VAL;
+    if (!(qp > 1.0) || !(qs > 1.0))
+      return fail(BBFD_EMATERIAL, "material %d: quality factor <= 1 (Q_P %g, Q_S %g)", m, qp, qs);
+    // One Zener mechanism at omega0: Q(omega0) = (2 + tau)/tau  ->  tau = 2/(Q - 1).
+    const double tp = std::isinf(qp) ? 0.0 : 2.0 / (qp - 1.0);
+    const double ts = std::isinf(qs) ? 0.0 : 2.0 / (qs - 1.0);
+    const double pir = q.rho * q.c_l * q.c_l * relaxed_factor(tp);
+    const double mur = q.rho * q.c_s * q.c_s * relaxed_factor(ts);
+    const double piu = pir * (1.0 + tp), muu = mur * (1.0 + ts);
+    cmax = std::fmax(cmax, std::sqrt(piu / q.rho));
+    double *o = &pl->consts[9 * (size_t)m];
+    o[0] = qp; o[1] = qs; o[2] = tp; o[3] = ts; o[4] = pir; o[5] = mur; o[6] = piu; o[7] = muu;
+    o[8] = nu;
+  }
+  // Stability of the 4th-order staggered leapfrog in 3D: c dt/dx <= 1/(sqrt(3)(|c1|+|c2|)).
+  const double dt_max = dx / (std::sqrt(3.0) * (kC1 - kC2) * cmax);
+  const int nt = (int)std::ceil(T / (p->cfl_safety * dt_max));
+  const double dt = T / nt;
+  const int ks = p->source_k < 0 ? p->pml : p->source_k;
+  if (ks < p->pml || ks >= p->nz - p->pml)
+    return fail(BBFD_EGEOMETRY, "source plane %d inside the absorbing layer", ks);
+  int cap = p->capture_start < 0 ? p->n_steps - 2 * nt : p->capture_start;
+  if (cap < 0) cap = 0;
+  if (cap > p->n_steps) return fail(BBFD_EINVAL, "capture_start beyond n_steps");
+  pl->dx = dx; pl->dt = dt; pl->omega = w0; pl->cmax = cmax; pl->nt = nt; pl->cap = cap; pl->ks = ks;
+  pl->d0 = p->pml > 0 ? 3.0 * cmax * std::log(1.0 / kPmlR0) / (2.0 * p->pml * dx) : 0.0;
+  return BBFD_OK;
+}
+
+// CPML damping at coordinate xi (cells, integer or half-integer) along an axis
+// of n cells with an L-cell layer: quadratic profile, b = exp(-d dt), a = b - 1.
+void pml_coeff(const bbfd_plan *pl, int n, double xi, float *b, float *a) {
+  const int L = pl->prob.pml;
+  double depth = 0.0;
+  if (L > 0) depth = std::fmax(0.0, std::fmax((L - 0.5) - xi, xi - (n - L - 0.5)));
+  if (depth <= 0.0) {
+    *b = 1.0f;
+    *a = 0.0f;
+    return;
+  }
+  const double d = pl->d0 * (depth / L) * (depth / L);
+  *b = (float)std::exp(-d * pl->dt);
+  *a = (float)std::expm1(-d * pl->dt);
+}
+
+int build_tables(bbfd_plan *pl) {
+  const bbfd_problem &p = pl->prob;
+  pl->lut.assign((size_t)p.n_materials * kLutW, 0.0f);
+  pl->pmltab.resize((size_t)p.nx + p.ny + p.nz);
+  const double s = pl->dt / pl->dx;
+  for (int m = 0; m < p.n_materials; ++m) {
+    const double *c = &pl->consts[9 * (size_t)m];
+    float *o = pl->lut.data() + m * kLutW;
+    o[kRhoS] = (float)(pl->mats[m].rho / s);
+    o[kPiU] = (float)(c[6] * s);
+    o[kMuU] = (float)(c[7] * s);
+    o[kPiTau] = (float)(c[4] * c[2] * s);
+    o[kMuTau] = (float)(c[5] * c[3] * s);
+    o[kTauS] = (float)c[3];
+    o[kInvMu] = c[5] > 0 ? (float)(1.0 / (c[5] * s)) : INFINITY;
+  }
+  const int dims[3] = {p.nx, p.ny, p.nz};
+  float4 *t = pl->pmltab.data();
+  for (int ax = 0; ax < 3; ++ax)
+    for (int i = 0; i < dims[ax]; ++i, ++t) {
+      pml_coeff(pl, dims[ax], (double)i, &t->x, &t->y);
+      pml_coeff(pl, dims[ax], i + 0.5, &t->z, &t->w);
+    }
+  const double h = 0.5 * pl->omega * pl->dt;  // dt / (2 tau_sigma), tau_sigma = 1/omega0
+  pl->relax_a = (float)((1.0 - h) / (1.0 + h));
+  pl->relax_b = (float)(2.0 * h / (1.0 + h));
+  // Soft source per step, evaluated at t = (n + 1/2) dt: two-period sin^2 ramp,
+  // strength 2 c_w dt / dx so each outgoing wave carries |S|.
+  pl->src_c.resize(p.n_steps);
+  pl->src_s.resize(p.n_steps);
+  const double T = 1.0 / p.freq_hz;
+  for (int n = 0; n < p.n_steps; ++n) {
+    const double t = (n + 0.5) * pl->dt;
+    double w = 1.0;
+    if (t < 2.0 * T) {
+      const double q = std::sin(kPi * t / (4.0 * T));
+      w = q * q;
+    }
+    const double amp = pl->dt * 2.0 * kCw / pl->dx * w;
+    pl->src_c[n] = (float)(amp * std::cos(pl->omega * t));
+    pl->src_s[n] = (float)(amp * std::sin(pl->omega * t));
+  }
+  return BBFD_OK;
+}
+
+void layout(bbfd_plan *pl) {
+  const bbfd_problem &p = pl->prob;
+  Grid &g = pl->g;
+  g.nx = p.nx; g.ny = p.ny; g.nz = p.nz; g.L = p.pml; g.ks = pl->ks;
+  g.pitch = (int)round_up((size_t)p.nx + 2 * kGhost, 32);
+  g.rows = p.ny + 2 * kGhost;
+  g.plane = (long long)g.pitch * g.rows;
+  g.stride = (long long)round_up(kX0 + (size_t)g.plane * (p.nz + 2 * kGhost), 64);
+  const long long nbxy = (long long)((p.nx + 63) / 64) * ((p.ny + 3) / 4);
+  long long kc = (nbxy * p.nz + 4095) / 4096;
+  pl->kchunk = (int)std::max(1LL, std::min<long long>(kc, p.nz));
+  size_t o = 0;
+  pl->off_status = o; o += 256;
+  pl->off_lut = o; o += round_up(256 * kLutW * sizeof(float), 256);
+  pl->off_pml = o; o += round_up(((size_t)p.nx + p.ny + p.nz) * sizeof(float4), 256);
+  pl->off_pv = o; o += round_up(argmax_partials() * sizeof(float), 256);
+  pl->off_pi = o; o += round_up(argmax_partials() * sizeof(long long), 256);
+  pl->off_idx = o; o += round_up((size_t)g.stride, 256);
+  pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
+  pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
+  pl->ws_bytes = o;
+}
+
+int check_ws(const bbfd_plan *pl, const void *ws, uint64_t bytes) {
+  if (!ws) return fail(BBFD_ENOMEM, "null workspace");
+  if ((uintptr_t)ws % 256) return fail(BBFD_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < pl->ws_bytes)
+    return fail(BBFD_ENOMEM, "workspace of %llu bytes, need %llu", (unsigned long long)bytes,
+                (unsigned long long)pl->ws_bytes);
+  return BBFD_OK;
+}
+
+StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float *peak, char *ws) {
+  StepArgs a{};
+  a.g = pl->g;
+  a.idx = (const uint8_t *)(ws + pl->off_idx);
+  a.lut = (const float *)(ws + pl->off_lut);
+  const float4 *t = (const float4 *)(ws + pl->off_pml);
+  a.pml.x = t;
+  a.pml.y = t + pl->prob.nx;
+  a.pml.z = t + pl->prob.nx + pl->prob.ny;
+  for (int f = 0; f < kNState; ++f)
+    a.f[f] = (float *)(ws + pl->off_state) + (size_t)f * pl->g.stride;
+  for (int f = 0; f < kNPsi; ++f)
+    a.psi[f] = (float *)(ws + pl->off_psi) + (size_t)f * pl->g.stride;
+  a.src = (const float2 *)src;
+  a.peak = peak;
+  a.relax_a = pl->relax_a;
+  a.relax_b = pl->relax_b;
+  a.kchunk = pl->kchunk;
+  return a;
+}
+
+// Pinned staging copies of the host tables (device uploads stay asynchronous
+// and capturable); made once, at the first solve, under the plan's mutex.
+int ensure_pinned(bbfd_plan *pl) {
+  if (pl->h_lut) return BBFD_OK;
+  hipError_t e;
+  float *lut = nullptr;
+  float4 *pml = nullptr;
+  if ((e = hipHostMalloc((void **)&lut, pl->lut.size() * sizeof(float), hipHostMallocDefault)) !=
+      hipSuccess)
+    return hip_fail(e, "pinned LUT allocation");
+  if ((e = hipHostMalloc((void **)&pml, pl->pmltab.size() * sizeof(float4), hipHostMallocDefault)) !=
+      hipSuccess) {
+    (void)hipHostFree(lut);
+    return hip_fail(e, "pinned layer-table allocation");
+  }
+  std::memcpy(lut, pl->lut.data(), pl->lut.size() * sizeof(float));
+  std::memcpy(pml, pl->pmltab.data(), pl->pmltab.size() * sizeof(float4));
+  pl->h_pml = pml;
+  pl->h_lut = lut;
+  return BBFD_OK;
+}
+
+// Enqueue one whole solve on s (no synchronisation).  With ev != NULL (direct
+// launches only), ev[2n] / ev[2n+1] / ev[2n+2] bracket step n's two kernels.
+int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
+                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+  const bbfd_problem &p = pl->prob;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(ws + pl->off_lut, pl->h_lut, (size_t)p.n_materials * kLutW * sizeof(float),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "LUT upload");
+  if ((e = hipMemcpyAsync(ws + pl->off_pml, pl->h_pml,
+                          ((size_t)p.nx + p.ny + p.nz) * sizeof(float4), hipMemcpyHostToDevice,
+                          s)) != hipSuccess)
+    return hip_fail(e, "layer-table upload");
+  if ((e = launch_fill((float *)(ws + pl->off_status), 256 / sizeof(float), 0.f, s)) != hipSuccess)
+    return hip_fail(e, "status clear");
+  if ((e = launch_fill((float *)(ws + pl->off_state),
+                       (long long)(kNState + kNPsi) * pl->g.stride, 0.f, s)) != hipSuccess)
+    return hip_fail(e, "state clear");
+  const long long cells = (long long)p.nx * p.ny * p.nz;
+  if ((e = launch_fill(peak, cells, 0.f, s)) != hipSuccess) return hip_fail(e, "peak clear");
+  Status *st = (Status *)(ws + pl->off_status);
+  if ((e = launch_pack(mat, (uint8_t *)(ws + pl->off_idx), pl->g, p.n_materials, &st->flags, s)) !=
+      hipSuccess)
+    return hip_fail(e, "index pack");
+  StepArgs a = step_args(pl, mat, src, peak, ws);
+  for (int n = 0; n < p.n_steps; ++n) {
+    a.src_c = pl->src_c[n];
+    a.src_s = pl->src_s[n];
+    a.capture = (n + 1 >= pl->cap) ? 1 : 0;
+    if (ev) {
+      (void)hipEventRecord(ev[2 * n], s);
+      if ((e = launch_velocity(a, s)) != hipSuccess) return hip_fail(e, "velocity launch");
+      (void)hipEventRecord(ev[2 * n + 1], s);
+      if ((e = launch_stress(a, s)) != hipSuccess) return hip_fail(e, "stress launch");
+    } else if ((e = launch_step(a, s)) != hipSuccess) {
+      return hip_fail(e, "step launch");
+    }
+  }
+  if (ev) (void)hipEventRecord(ev[2 * p.n_steps], s);
+  if ((e = launch_argmax(peak, p.nx, p.ny, p.nz, p.pml, (float *)(ws + pl->off_pv),
+                         (long long *)(ws + pl->off_pi), st, s)) != hipSuccess)
+    return hip_fail(e, "argmax launch");
+  return BBFD_OK;
+}
+
+int check_solve_args(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
+                     void *ws, uint64_t bytes) {
+  if (!pl) return fail(BBFD_EINVAL, "null plan");
+  if (!mat || !src || !peak) return fail(BBFD_EINVAL, "null device pointer");
+  return check_ws(pl, ws, bytes);
+}
+
+// Ring decomposition of the radiating surface (Section 2.3): rings no wider
+// than lambda/4, each split into the fewest equal elements of area at most
+// lambda^2/16.  e1 is e_x projected off the axis (e_y when the axis lies within
+// ~26 degrees of x); e2 = axis x e1.
+int make_elements(const bbfd_transducer *t, double freq, std::vector<double> &out) {
+  if (!t) return fail(BBFD_EINVAL, "null transducer");
+  if (!(t->radius_m > 0)) return fail(BBFD_EINVAL, "transducer radius must be positive");
+  double ax[3] = {t->axis[0], t->axis[1], t->axis[2]};
+  const double an = std::sqrt(ax[0] * ax[0] + ax[1] * ax[1] + ax[2] * ax[2]);
+  if (!(an > 0)) return fail(BBFD_EINVAL, "zero transducer axis");
+  for (double &v : ax) v /= an;
+  double ref[3] = {1.0, 0.0, 0.0};
+  if (std::fabs(ax[0]) >= 0.9) { ref[0] = 0.0; ref[1] = 1.0; }
+  const double dr = ref[0] * ax[0] + ref[1] * ax[1] + ref[2] * ax[2];
+  double e1[3], e2[3];
+  for (int a = 0; a < 3; ++a) e1[a] = ref[a] - dr * ax[a];
+  const double n1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (double &v : e1) v /= n1;
+  e2[0] = ax[1] * e1[2] - ax[2] * e1[1];
+  e2[1] = ax[2] * e1[0] - ax[0] * e1[2];
+  e2[2] = ax[0] * e1[1] - ax[1] * e1[0];
+  const double lam = kCw / freq;
+  const double area_max = lam * lam / 16.0, width = lam / 4.0;
+  out.clear();
+  auto push = [&](const double p[3], double area) {
+    out.push_back(p[0]); out.push_back(p[1]); out.push_back(p[2]); out.push_back(area);
+  };
+  if (t->kind == 0) {
+    const int nr = (int)std::ceil(t->radius_m / width);
+    const double dr_ = t->radius_m / nr;
+    for (int r = 0; r < nr; ++r) {
+      const double r0 = r * dr_, r1 = (r + 1) * dr_, rm = 0.5 * (r0 + r1);
+      const double ring = kPi * (r1 * r1 - r0 * r0);
+      const long nphi = std::max(1L, (long)std::ceil(ring / area_max));
+      for (long q = 0; q < nphi; ++q) {
+        const double ph = 2.0 * kPi * (q + 0.5) / nphi, c = std::cos(ph), s = std::sin(ph);
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = t->apex_m[a] + rm * (c * e1[a] + s * e2[a]);
+        push(p, ring / nphi);
+      }
+    }
+  } else if (t->kind == 1) {
+    const double F = t->focal_m;
+    if (!(F >= t->radius_m)) return fail(BBFD_EINVAL, "bowl aperture radius exceeds its curvature radius");
+    const double thmax = std::asin(t->radius_m / F);
+    const int nr = (int)std::ceil(F * thmax / width);
+    const double dth = thmax / nr;
+    double focus[3];
+    for (int a = 0; a < 3; ++a) focus[a] = t->apex_m[a] + F * ax[a];
+    for (int r = 0; r < nr; ++r) {
+      const double t0 = r * dth, t1 = (r + 1) * dth, tm = 0.5 * (t0 + t1);
+      const double ring = 2.0 * kPi * F * F * (std::cos(t0) - std::cos(t1));
+      const long nphi = std::max(1L, (long)std::ceil(ring / area_max));
+      const double ct = std::cos(tm), st = std::sin(tm);
+      for (long q = 0; q < nphi; ++q) {
+        const double ph = 2.0 * kPi * (q + 0.5) / nphi, c = std::cos(ph), s = std::sin(ph);
+        double p[3];
+        for (int a = 0; a < 3; ++a) p[a] = focus[a] + F * (-ct * ax[a] + st * (c * e1[a] + s * e2[a]));
+        push(p, ring / nphi);
+      }
+    }
+  } else {
+    return fail(BBFD_EINVAL, "unknown transducer kind %d", t->kind);
+  }
+  return BBFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bbfd_last_error(void) { return g_err.c_str(); }
+
+int bbfd_plan_create(const bbfd_problem *problem, bbfd_plan **out) {
+  if (!out) return fail(BBFD_EINVAL, "null output pointer");
+  *out = nullptr;
+  bbfd_plan *pl = new (std::nothrow) bbfd_plan();
+  if (!pl) return fail(BBFD_EINVAL, "out of host memory");
+  int rc = validate_and_derive(problem, pl);
+  if (rc == BBFD_OK) rc = build_tables(pl);
+  if (rc != BBFD_OK) {
+    bbfd_plan_destroy(pl);
+    return rc;
+  }
+  layout(pl);
+  *out = pl;
+  return BBFD_OK;
+}
+
+void bbfd_plan_destroy(bbfd_plan *pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  if (pl->h_lut) (void)hipHostFree(pl->h_lut);
+  if (pl->h_pml) (void)hipHostFree(pl->h_pml);
+  delete pl;
+}
+
+int bbfd_plan_get_info(const bbfd_plan *pl, bbfd_plan_info *out) {
+  if (!pl || !out) return fail(BBFD_EINVAL, "null argument");
+  out->dx = pl->dx;
+  out->dt = pl->dt;
+  out->c_max = pl->cmax;
+  out->steps_per_period = pl->nt;
+  out->capture_start = pl->cap;
+  out->source_k = pl->ks;
+  out->pitch = pl->g.pitch;
+  out->workspace_bytes = pl->ws_bytes;
+  out->cells = (uint64_t)pl->prob.nx * pl->prob.ny * pl->prob.nz;
+  return BBFD_OK;
+}
+
+int bbfd_material_constants(const bbfd_plan *pl, double *out, int32_t n_rows) {
+  if (!pl || !out) return fail(BBFD_EINVAL, "null argument");
+  if (n_rows < pl->prob.n_materials) return fail(BBFD_EINVAL, "need %d rows", pl->prob.n_materials);
+  std::memcpy(out, pl->consts.data(), pl->consts.size() * sizeof(double));
+  return BBFD_OK;
+}
+
+int bbfd_transducer_elements(const bbfd_plan *pl, const bbfd_transducer *t, double *xyza,
+                             int64_t cap, int64_t *n_out) {
+  if (!pl || !n_out) return fail(BBFD_EINVAL, "null argument");
+  std::vector<double> el;
+  int rc = make_elements(t, pl->prob.freq_hz, el);
+  if (rc) return rc;
+  const int64_t n = (int64_t)(el.size() / 4);
+  *n_out = n;
+  if (xyza) std::memcpy(xyza, el.data(), (size_t)std::min(n, cap) * 4 * sizeof(double));
+  return BBFD_OK;
+}
+
+int bbfd_source_rayleigh(const bbfd_plan *pl, const bbfd_transducer *t, float *src,
+                         void *workspace, uint64_t bytes, void *stream) {
+  if (!pl || !src) return fail(BBFD_EINVAL, "null argument");
+  int rc = check_ws(pl, workspace, bytes);
+  if (rc) return rc;
+  std::vector<double> el;
+  if ((rc = make_elements(t, pl->prob.freq_hz, el))) return rc;
+  const size_t n = el.size() / 4;
+  const double zs = pl->ks * pl->dx;
+  for (size_t e = 0; e < n; ++e)
+    if (!(el[4 * e + 2] < zs))
+      return fail(BBFD_EGEOMETRY, "transducer element %zu at z %.4g m is not before the source plane (%.4g m)",
+                  e, el[4 * e + 2], zs);
+  const size_t need = n * sizeof(double4);
+  if (need > (size_t)kNState * pl->g.stride * sizeof(float))
+    return fail(BBFD_ENOMEM, "too many elements (%zu) for the workspace", n);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  hipError_t e = hipMemcpyAsync(ws + pl->off_state, el.data(), need, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "element upload");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "element upload sync");
+  const double kw = pl->omega / kCw;
+  const double pre = pl->omega * kRhoW * t->u0 / (2.0 * kPi);
+  e = launch_rayleigh((const double4 *)(ws + pl->off_state), (int)n, pl->prob.nx, pl->prob.ny,
+                      pl->dx, zs, kw, pre, (float2 *)src, s);
+  if (e != hipSuccess) return hip_fail(e, "rayleigh launch");
+  return BBFD_OK;
+}
+
+int bbfd_solve_direct(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float *peak,
+                      void *workspace, uint64_t bytes, void *stream) {
+  int rc = check_solve_args(cpl, mat, src, peak, workspace, bytes);
+  if (rc) return rc;
+  bbfd_plan *pl = const_cast<bbfd_plan *>(cpl);  // pinned staging only
+  {
+    std::lock_guard<std::mutex> lock(pl->mu);
+    if ((rc = ensure_pinned(pl))) return rc;
+  }
+  return enqueue_solve(pl, mat, src, peak, (char *)workspace, (hipStream_t)stream);
+}
+
+int bbfd_solve_profiled(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float *peak,
+                        void *workspace, uint64_t bytes, void *stream, double *ms_out) {
+  int rc = check_solve_args(cpl, mat, src, peak, workspace, bytes);
+  if (rc) return rc;
+  if (!ms_out) return fail(BBFD_EINVAL, "null timing output");
+  bbfd_plan *pl = const_cast<bbfd_plan *>(cpl);
+  {
+    std::lock_guard<std::mutex> lock(pl->mu);
+    if ((rc = ensure_pinned(pl))) return rc;
+  }
+  const int n = pl->prob.n_steps;
+  std::vector<hipEvent_t> ev(2 * (size_t)n + 1, nullptr);
+  hipError_t e = hipSuccess;
+  for (auto &x : ev)
+    if ((e = hipEventCreate(&x)) != hipSuccess) break;
+  if (e == hipSuccess) {
+    hipStream_t s = (hipStream_t)stream;
+    rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, s, ev.data());
+    if (rc == BBFD_OK && (e = hipEventSynchronize(ev.back())) != hipSuccess)
+      rc = hip_fail(e, "profiled solve sync");
+    double tv = 0.0, ts = 0.0;
+    for (int k = 0; rc == BBFD_OK && k < n; ++k) {
+      float a = 0.f, b = 0.f;
+      if (hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]) != hipSuccess ||
+          hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2]) != hipSuccess) {
+        rc = fail(BBFD_EHIP, "event timing");
+        break;
+      }
+      tv += a;
+      ts += b;
+    }
+    ms_out[0] = tv;
+    ms_out[1] = ts;
+  } else {
+    rc = hip_fail(e, "event create");
+  }
+  for (auto &x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return rc;
+}
+
+int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float *peak,
+               void *workspace, uint64_t bytes, void *stream) {
+  int rc = check_solve_args(cpl, mat, src, peak, workspace, bytes);
+  if (rc) return rc;
+  bbfd_plan *pl = const_cast<bbfd_plan *>(cpl);  // graph cache only
+  std::lock_guard<std::mutex> lock(pl->mu);
+  if ((rc = ensure_pinned(pl))) return rc;
+  const void *key[4] = {mat, src, peak, workspace};
+  if (!pl->exec || std::memcmp(key, pl->key, sizeof key) != 0) {
+    if (pl->exec) { (void)hipGraphExecDestroy(pl->exec); pl->exec = nullptr; }
+    if (pl->graph) { (void)hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+    hipError_t e;
+    if (!pl->cap_stream &&
+        (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "capture stream");
+    if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, pl->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(pl->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    pl->graph = g;
+    if ((e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      pl->exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    std::memcpy(pl->key, key, sizeof key);
+  }
+  hipError_t e = hipGraphLaunch(pl->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return BBFD_OK;
+}
+
+int bbfd_status(const bbfd_plan *pl, const void *workspace, int64_t *peak_index,
+                float *peak_value, void *stream) {
+  if (!pl || !workspace) return fail(BBFD_EINVAL, "null argument");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream sync");
+  Status st{};
+  e = hipMemcpy(&st, (const char *)workspace + pl->off_status, sizeof st, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "status read");
+  if (peak_index) *peak_index = st.peak_index;
+  if (peak_value) *peak_value = st.peak_value;
+  if (st.flags & kStatusIndex) return fail(BBFD_EINDEX, "material index >= n_materials in the map");
+  if (st.flags & kStatusDiverged) return fail(BBFD_EDIVERGED, "non-finite peak pressure (diverged)");
+  return BBFD_OK;
+}
+
+}  // extern "C"

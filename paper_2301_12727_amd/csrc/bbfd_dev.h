@@ -1,0 +1,85 @@
+// Device-side data layout shared by the HIP kernels and the host side of the
+// library.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbfd {
+
+// Padded field layout: every field array holds the interior (nx, ny, nz) plus
+// two zero ghost cells on each side, x fastest.  Rows are `pitch` floats apart
+// (pitch >= nx + 4, multiple of 32) and every row's interior starts on a
+// 128-byte boundary, so interior cell (i, j, k) sits at
+//   kX0 + ((k + 2) * rows + (j + 2)) * pitch + i,   rows = ny + 4.
+// Ghost slots i = -2, -1 of a row alias the unused tail of the previous row.
+constexpr int kX0 = 32;
+constexpr int kGhost = 2;
+
+struct Grid {
+  int nx, ny, nz;
+  int pitch;      // floats between consecutive rows
+  int rows;       // ny + 4
+  int L;          // absorbing layer thickness (cells)
+  int ks;         // source plane
+  long long plane;   // pitch * rows
+  long long stride;  // elements per padded array (multiple of 64)
+  __host__ __device__ long long off(int i, int j, int k) const {
+    return kX0 + ((long long)(k + kGhost) * rows + (j + kGhost)) * pitch + i;
+  }
+};
+
+// Per-material FP32 table (host-derived in FP64, scaled by dt/dx):
+enum LutField {
+  kRhoS = 0,   // rho * dx / dt           (buoyancy of a face: 2 / (rhoS_a + rhoS_b))
+  kPiU = 1,    // pi_U * dt / dx          (unrelaxed P modulus)
+  kMuU = 2,    // mu_U * dt / dx          (unrelaxed shear modulus)
+  kPiTau = 3,  // pi_R * tau_P * dt / dx  (memory-variable target, normal part)
+  kMuTau = 4,  // mu_R * tau_S * dt / dx  (memory-variable target, shear part)
+  kTauS = 5,   // tau_S                   (edge average)
+  kInvMu = 6,  // dx / (mu_R * dt), +inf for fluids (edge harmonic mean)
+  kLutW = 8
+};
+
+// State array slots inside the workspace.
+enum Field {
+  VX = 0, VY, VZ, SXX, SYY, SZZ, SXY, SXZ, SYZ, RXX, RYY, RZZ, RXY, RXZ, RYZ, kNState
+};
+// 18 CPML memories: 9 for the stress derivatives of the velocity update and 9
+// for the velocity derivatives of the stress update.
+constexpr int kNPsi = 18;
+
+// CPML coefficient table per axis: 4 floats per index
+//   [b at integer position, a at integer, b at half position i+1/2, a at half]
+// with b = exp(-d dt), a = b - 1; b = 1, a = 0 where the profile is zero.
+struct PmlTab {
+  const float4 *x, *y, *z;
+};
+
+struct StepArgs {
+  Grid g;
+  const uint8_t *idx;     // padded, replicated ghosts
+  const float *lut;       // kLutW floats per material
+  PmlTab pml;
+  float *f[kNState];      // padded state arrays
+  float *psi[kNPsi];      // padded CPML memories (touched in the layer only)
+  const float2 *src;      // [ny][nx] source plane
+  float *peak;            // [nz][ny][nx]
+  float relax_a;          // (1 - h) / (1 + h), h = omega dt / 2
+  float relax_b;          // 2 h / (1 + h)
+  float src_c, src_s;     // per step: dp = src_c * Re S - src_s * Im S
+  int capture;            // 1: update the peak map after this step
+  int kchunk;             // z cells per block
+};
+
+// Device status block at the front of the workspace.
+struct Status {
+  int flags;       // bit 0: index out of range; bit 1: non-finite peak
+  int pad;
+  float peak_value;
+  int pad2;
+  long long peak_index;
+};
+constexpr int kStatusIndex = 1;
+constexpr int kStatusDiverged = 2;
+
+}  // namespace bbfd

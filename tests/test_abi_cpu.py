@@ -1,0 +1,95 @@
+"""C-ABI library: loads, exports every declared symbol, and its host-side logic
+(validation, FP64 material/time-step derivation, transducer elements) agrees
+with the oracle.  No GPU needed: no device call is made here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2301_12727_amd as bb
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            names += re.findall(r"^\s*(?:int|void|const char \*)\s*(\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(bb.bbfd.LIB_PATH)
+    names = declared_functions()
+    assert "bbfd_solve" in names and "bbfd_source_rayleigh" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(bb.EXPORTS) <= set(names)
+
+
+def test_material_constants_match_oracle():
+    for case in (synth.plate_case(), synth.skull_case(48, 48, 48, 700e3, 6.0, 100, build_map=False)):
+        for qc in (1.0, 3.0):
+            plan = bb.Plan.from_case(case, qc=qc)
+            mc = plan.material_constants()
+            info, oc = oracle.setup(oracle.problem_from_case(case, qc=qc))
+            ref = np.array([[d[k] for k in ("q_p", "q_s", "tau_p", "tau_s", "pi_r", "mu_r", "pi_u",
+                                             "mu_u", "nu")] for d in oc])
+            fin = np.isfinite(ref)
+            assert np.array_equal(fin, np.isfinite(mc))
+            np.testing.assert_allclose(mc[fin], ref[fin], rtol=1e-13, atol=1e-300)
+            assert plan.info["steps_per_period"] == info["steps_per_period"]
+            assert plan.info["dt"] == pytest.approx(info["dt"], rel=1e-15)
+            assert plan.info["capture_start"] == info["capture_start"]
+            assert plan.info["source_k"] == info["source_k"]
+
+
+def test_elements_match_oracle():
+    cases = [synth.plate_case(), synth.skull200(build_map=False), synth.skull400(build_map=False)]
+    cases += synth.batch_cases(6, build_map=False)
+    for case in cases:
+        plan = bb.Plan.from_case(case, n_steps=10)
+        a = plan.elements(case.transducer)
+        b = oracle.elements(case.transducer, case.freq_hz)
+        assert a.shape == b.shape
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=0), bb.EINVAL),
+    (dict(pml=40), bb.EINVAL),
+    (dict(n_steps=0), bb.EINVAL),
+    (dict(ppw=-1.0), bb.EINVAL),
+    (dict(source_k=3), bb.EGEOMETRY),
+    (dict(capture_start=10_000), bb.EINVAL),
+    (dict(materials=np.array([[1000.0, 1500.0, 0, 0, 0], [1900.0, 2000.0, 1800.0, 0, 0]])),
+     bb.EMATERIAL),
+    (dict(materials=np.array([[1000.0, 1500.0, 0, 0, 0], [1900.0, 2800.0, 1500.0, 5000.0, 0]])),
+     bb.EMATERIAL),
+    (dict(materials=np.array([[0.0, 1500.0, 0, 0, 0]])), bb.EMATERIAL),
+])
+def test_plan_rejects(bad, code):
+    kw = dict(nx=64, ny=64, nz=64, freq_hz=250e3, ppw=6.0, n_steps=100,
+              materials=np.array([synth.table1(250e3)["water"], synth.PLATE]))
+    kw.update(bad)
+    with pytest.raises(bb.BBFDError) as e:
+        bb.Plan(**kw)
+    assert e.value.code == code
+    assert bb.lib().bbfd_last_error().decode()
+
+
+def test_workspace_layout_fits_every_workload():
+    for case in (synth.plate_case(), synth.skull200(build_map=False),
+                 synth.skull400(build_map=False)):
+        plan = bb.Plan.from_case(case)
+        cells_padded = plan.info["pitch"] * (case.ny + 4) * (case.nz + 4)
+        # 15 state + 18 absorbing-layer memories (FP32) + 1-byte index, padded
+        assert plan.workspace_bytes >= 33 * 4 * cells_padded + cells_padded
+        assert plan.workspace_bytes < 1.2 * (33 * 4 + 1) * cells_padded + (1 << 20)
+        assert plan.info["pitch"] % 32 == 0 and plan.info["pitch"] >= case.nx + 4
