@@ -65,16 +65,17 @@ def algorithmic_bytes(case, info) -> dict:
     """Bytes each kernel must move per launch at perfect on-chip reuse (FP32
     state, 1-byte index), averaged over the time loop.
       velocity: read 6 stresses + 3 velocities + index, write 3 velocities
-                = 49 B/cell, + 3 layer memories read+write (24 B) per slab cell
+                = 49 B/cell, + 3 layer memories read+write (24 B) per slab cell,
+                + the source plane (8 B per column)
       stress:   read 3 velocities + 6 stresses + 6 memories + index, write 6 +
                 6 = 109 B/cell, + 3 layer memories (24 B) per slab cell,
-                + 8 B/cell (peak read+write) in capture steps, + source plane."""
+                + 8 B/cell (peak read+write) in capture steps."""
     cells = case.cells
     slabs = sum(slab_cells(case))
     steps = case.n_steps
     cap_steps = steps - info["capture_start"]
-    vel = 49 * cells + 24 * slabs
-    stress = 109 * cells + 24 * slabs + 8 * cells * cap_steps / steps + 8 * case.nx * case.ny
+    vel = 49 * cells + 24 * slabs + 8 * case.nx * case.ny
+    stress = 109 * cells + 24 * slabs + 8 * cells * cap_steps / steps
     return {"velocity": vel, "stress": stress, "per_cell_update": (vel + stress) / cells}
 
 
@@ -113,6 +114,62 @@ def cpu_baseline(case, sample_steps: int = 2) -> dict:
                       f"step ({dt:.1f} s, FP64, OpenMP)"}
 
 
+TUNE_CACHE = os.path.join(ROOT, "paper_2301_12727_amd", "tune_cache.txt")
+
+
+def batched_section(bb, torch, n_solves: int = 32) -> dict:
+    """Uneven sweep (sizes 96..160 per axis, 250/500/700 kHz, tilted bowls): one
+    captured persistent launch for all solves vs the same solves run one after
+    another as plain captured solves.  Both sides include no Rayleigh time."""
+    import numpy as np
+    import synth
+    cases = synth.batch_cases(n_solves)
+    dev = torch.device("cuda:0")
+    b = bb.Batch(cases)
+    ws = b.workspace(dev)
+    mats = [torch.from_numpy(c.mat).to(dev) for c in cases]
+    srcs = [torch.empty((c.ny, c.nx), dtype=torch.complex64, device=dev) for c in cases]
+    peaks = [torch.empty((c.nz, c.ny, c.nx), dtype=torch.float32, device=dev) for c in cases]
+    for i, c in enumerate(cases):
+        b.source_rayleigh(i, c.transducer, srcs[i], ws)
+    t0 = time.perf_counter()
+    best, shape = b.autotune(mats, srcs, peaks, ws, cache_path=TUNE_CACHE, probe_steps=10)
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] batched shape {shape} (autotune {tune_s:.1f} s)")
+    b.solve(mats, srcs, peaks, ws)                     # capture + warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.solve(mats, srcs, peaks, ws)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    for i in range(n_solves):
+        b.status(ws, i)
+    log(f"[bench] batched sweep {t_batch:.3f} s")
+    plans = [bb.Plan.from_case(c) for c in cases]
+    wss = [p.workspace(dev) for p in plans]
+    seq = [torch.empty_like(p) for p in peaks]
+    for p, w, m, sr, o in zip(plans, wss, mats, srcs, seq):   # capture + warm
+        p.solve(m, sr, o, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, w, m, sr, o in zip(plans, wss, mats, srcs, seq):
+        p.solve(m, sr, o, w)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    equal = all(bool(torch.equal(a, c)) for a, c in zip(peaks, seq))
+    updates = sum(c.cells * c.n_steps for c in cases)
+    log(f"[bench] sequential {t_seq:.3f} s; maps equal {equal}")
+    del np
+    return {"solves": n_solves, "batched_solves_per_s": round(n_solves / t_batch, 3),
+            "sequential_solves_per_s": round(n_solves / t_seq, 3),
+            "speedup": round(t_seq / t_batch, 3),
+            "batched_gcell_updates_per_s": round(updates / t_batch / 1e9, 3),
+            "shape": {"rows_per_block": shape[0], "blocks": shape[1], "kchunk": shape[2],
+                      "tiles": shape[3]},
+            "autotune_s": round(tune_s, 2), "maps_equal_to_plain_solves": equal,
+            "cells": int(sum(c.cells for c in cases))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +178,11 @@ def main():
     ap.add_argument("--workload", default="skull400", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-sweep section")
+    ap.add_argument("--time-steps", type=int, default=None,
+                    help="override the workload's time-step count (short profiling runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -131,7 +193,19 @@ def main():
     import torch
     import paper_2301_12727_amd as bb
 
+    if args.calibrate_copy:
+        n = 1 << 28                       # 2^28 floats = 1 GiB read + 1 GiB written
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "repeats": 5}))
+        return
+
     case = WORKLOADS[args.workload]()
+    if args.time_steps:
+        case.n_steps = args.time_steps
     log(f"[bench] workload {case.name}: {case.nx}x{case.ny}x{case.nz}, {case.n_steps} steps")
     plan = bb.Plan.from_case(case)
     info = plan.info
@@ -195,6 +269,10 @@ def main():
         "effective_hbm_gbs": round(value * ab["per_cell_update"], 1),
         "roofline": roof,
     }
+    del ws, mat, src, peak
+    torch.cuda.empty_cache()
+    out["batched"] = None if args.no_batch else batched_section(bb, torch)
+    torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

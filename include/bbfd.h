@@ -103,7 +103,7 @@ int bbfd_transducer_elements(const bbfd_plan *plan, const bbfd_transducer *t, do
                              int64_t cap, int64_t *n_out);
 
 /* Rayleigh-Sommerfeld field of the transducer radiating into water (Section
-   2.3) at the cell centres of the source plane:
+   2.3) on the source plane z = (source_k + 1/2) dx at the (x, y) cell centres:
      S(x) = (i omega rho_w / 2 pi) sum_e u0 A_e exp(-i k R_e) / R_e
    (e^{+i omega t}); src_re_im (dev) receives 2*nx*ny floats, (re, im)
    interleaved, [ny][nx].  Uses the front of the workspace to stage the
@@ -112,8 +112,17 @@ int bbfd_transducer_elements(const bbfd_plan *plan, const bbfd_transducer *t, do
 int bbfd_source_rayleigh(const bbfd_plan *plan, const bbfd_transducer *t, float *src_re_im,
                          void *workspace, uint64_t workspace_bytes, void *stream);
 
-/* Full FDTD solve (Eq. 1 with memory variables, absorbing layer, soft source,
-   peak capture), enqueued on stream:
+/* The same Rayleigh-Sommerfeld field in water at every cell centre of the
+   grid, field (dev) = 2*nx*ny*nz floats, complex [nz][ny][nx] (the free
+   field of the transducer; its phase is one of the surrogate's inputs).  Same
+   staging, blocking and geometry check as bbfd_source_rayleigh. */
+int bbfd_rayleigh_volume(const bbfd_plan *plan, const bbfd_transducer *t, float *field,
+                         void *workspace, uint64_t workspace_bytes, void *stream);
+
+/* Full FDTD solve (Eq. 1 with memory variables, absorbing layer, source,
+   peak capture), enqueued on stream.  The source field enters as a
+   normal-traction jump of 2 S across z = (source_k + 1/2) dx (a force layer on
+   the v_z faces there), ramped in over two periods.  Arguments:
      mat (dev)        uint8 [nz][ny][nx] material indices into the table
      src_re_im (dev)  complex source plane as written by bbfd_source_rayleigh
      peak (dev)       float [nz][ny][nx], receives max |p| over the capture
@@ -146,6 +155,47 @@ int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *
    output may be NULL. */
 int bbfd_status(const bbfd_plan *plan, const void *workspace, int64_t *peak_index,
                 float *peak_value, void *stream);
+
+/* ---- Batched sweeps: many independent solves of uneven size in one launch.
+   Each problem keeps its own grid, frequency, time step, tables and step count;
+   a persistent pair of kernels per time step walks a ragged (solve, tile)
+   table, solves dropping out of it once their own step count is reached, and
+   the whole sweep is captured in one HIP graph.  Results equal those of the
+   same problems solved one by one with bbfd_solve. */
+typedef struct bbfd_batch bbfd_batch;
+
+/* Creates one plan per problem (same validation and errors as
+   bbfd_plan_create, message prefixed with the problem index). */
+int bbfd_batch_create(const bbfd_problem *problems, int32_t n, bbfd_batch **out);
+void bbfd_batch_destroy(bbfd_batch *batch);
+/* workspace_bytes: device workspace of a batched solve (all solves plus the
+   tile/descriptor tables).  shape (may be NULL, 4 ints): rows per block,
+   persistent blocks, z cells per tile, number of tiles. */
+int bbfd_batch_info(const bbfd_batch *batch, uint64_t *workspace_bytes, int32_t *shape);
+/* Plan of solve i (owned by the batch) and the byte offset of its part of the
+   batch workspace, e.g. for bbfd_source_rayleigh on that solve. */
+const bbfd_plan *bbfd_batch_plan(const bbfd_batch *batch, int32_t i);
+uint64_t bbfd_batch_offset(const bbfd_batch *batch, int32_t i);
+/* Launch shape: by in {1, 2, 4, 8} rows per 64-wide block, blocks >= 1
+   persistent blocks, kchunk >= 1 z cells per tile (>= 4 when by = 1). */
+int bbfd_batch_set_shape(bbfd_batch *batch, int32_t by, int32_t blocks, int32_t kchunk);
+/* mat, src, peak: host arrays of n device pointers (layouts as bbfd_solve).
+   Captures on first use per pointer set and launch shape; enqueued on stream. */
+int bbfd_batch_solve(bbfd_batch *batch, const uint8_t *const *mat, const float *const *src,
+                     float *const *peak, void *workspace, uint64_t workspace_bytes, void *stream);
+/* bbfd_status for solve i of the last batched solve in this workspace. */
+int bbfd_batch_status(const bbfd_batch *batch, const void *workspace, int32_t i,
+                      int64_t *peak_index, float *peak_value, void *stream);
+/* Tile-shape autotuner: if cache_path names a file holding a line for this
+   sweep's size class ("gfx950:n<solves>:c<log1.01 cells>:s<max steps>"), applies
+   its shape; otherwise times probe_steps batched steps for every candidate
+   shape on these inputs (synchronising stream), applies the fastest, appends
+   it to cache_path (if given) and writes its time to *best_ms.  The workspace
+   contents are overwritten. */
+int bbfd_batch_autotune(bbfd_batch *batch, const uint8_t *const *mat, const float *const *src,
+                        float *const *peak, void *workspace, uint64_t workspace_bytes,
+                        void *stream, const char *cache_path, int32_t probe_steps,
+                        double *best_ms);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *bbfd_last_error(void);

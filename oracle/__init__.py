@@ -195,7 +195,8 @@ def rayleigh(el: np.ndarray, freq_hz: float, u0: float, pts: np.ndarray) -> np.n
 
 
 def source_plane(case, area_div: float = 16.0) -> np.ndarray:
-    """Rayleigh field on the source plane (cell centres), complex [ny, nx]."""
+    """Rayleigh field on the source plane z = (k_s + 1/2) dx at the (x, y) cell
+    centres, complex [ny, nx]."""
     t = case.transducer
     el = elements(t, case.freq_hz, area_div)
     dx = case.dx
@@ -203,7 +204,7 @@ def source_plane(case, area_div: float = 16.0) -> np.ndarray:
     if np.any(el[:, 2] >= ks * dx):
         raise OracleError(EGEOMETRY, "transducer crosses the source plane")
     jj, ii = np.meshgrid(np.arange(case.ny), np.arange(case.nx), indexing="ij")
-    pts = np.stack([ii * dx, jj * dx, np.full(ii.shape, ks * dx)], axis=-1)
+    pts = np.stack([ii * dx, jj * dx, np.full(ii.shape, (ks + 0.5) * dx)], axis=-1)
     return rayleigh(el, case.freq_hz, t.u0, pts).reshape(case.ny, case.nx)
 
 

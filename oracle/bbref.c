@@ -15,9 +15,11 @@
  *  - attenuation through one standard-linear-solid (Zener) mechanism per wave
  *    type relaxing at the drive frequency, sized from Q = q_c * omega/(2 c alpha)
  *    (Section 3.2, Eq. 3 and the q_c correction);
- *  - convolutional PML (quadratic profile, R0 = 1e-3) in an outer shell;
- *  - a soft isotropic stress source on the first interior plane carrying the
- *    Rayleigh-Sommerfeld field of the transducer (Section 2.3);
+ *  - convolutional PML with frequency shift (quadratic damping profile,
+ *    R0 = 1e-3, shift alpha = pi f0 decreasing linearly to 0 at the wall);
+ *  - the Rayleigh-Sommerfeld field S of the transducer (Section 2.3) entering
+ *    as a normal-stress (traction) jump of 2S across the plane
+ *    z = (k_s + 1/2) dx, i.e. a force layer on the v_z faces there;
  *  - capture of max |p|, p = -(sxx+syy+szz)/3, over the last two periods.
  */
 #include "bbref.h"
@@ -126,7 +128,8 @@ struct bbref_sim {
   int nm;
   double *rho, *pi_u, *mu_u, *pi_tau, *mu_tau, *tau_s, *mu;
   double *f[BBREF_NFIELDS];
-  double *pml_b[3]; /* per axis, index 2*xi+1: exp(-d(xi) dt), or 0 outside the layer */
+  double *pml_b[3]; /* per axis, index 2*xi+1: exp(-(d + alpha) dt), or 0 outside the layer */
+  double *pml_a[3]; /* per axis, index 2*xi+1: d/(d + alpha) (b - 1) */
   double *psi_v[9]; /* CPML memories of the 9 stress derivatives */
   double *psi_s[9]; /* CPML memories of the 9 velocity derivatives */
 };
@@ -196,21 +199,29 @@ static double pml_depth(const bbref_sim *s, int ax, double xi) {
   return l > 0 ? l : 0.0;
 }
 
-/* Quadratic damping profile d = d0 (depth/L)^2 turned into the per-step decay
-   b = exp(-d dt); 0 marks a coordinate outside the layer. */
-static double pml_decay(const bbref_sim *s, int ax, double xi) {
+/* Frequency-shifted CPML coefficients at depth l > 0 (cells): damping
+   d = d0 (l/L)^2, shift alpha = pi f0 (1 - l/L); per step b = exp(-(d + alpha) dt)
+   and a = d/(d + alpha) (b - 1).  b = 0 marks a coordinate outside the layer. */
+static void pml_coeffs(const bbref_sim *s, int ax, double xi, double *b, double *a) {
   double l = pml_depth(s, ax, xi);
-  if (l <= 0) return 0.0;
-  double damp = s->info.d0 * (l / s->L) * (l / s->L);
-  return exp(-damp * s->info.dt);
+  if (l <= 0) {
+    *b = 0.0;
+    *a = 0.0;
+    return;
+  }
+  double d = s->info.d0 * (l / s->L) * (l / s->L);
+  double al = M_PI * s->p.freq_hz * (1.0 - l / s->L);
+  *b = exp(-(d + al) * s->info.dt);
+  *a = d / (d + al) * (*b - 1.0);
 }
 
-/* Convolutional PML (kappa = 1, alpha = 0): psi <- b psi + (b - 1) d, and the
-   derivative used by the update becomes d + psi. */
+/* Convolutional PML (kappa = 1): psi <- b psi + a d, and the derivative used by
+   the update becomes d + psi. */
 static double cpml(const bbref_sim *s, double *psi, size_t c, int ax, double xi, double d) {
-  double b = s->pml_b[ax][(int)(2.0 * xi) + 1];
+  int m = (int)(2.0 * xi) + 1;
+  double b = s->pml_b[ax][m];
   if (b == 0.0) return d;
-  psi[c] = b * psi[c] + (b - 1.0) * d;
+  psi[c] = b * psi[c] + s->pml_a[ax][m] * d;
   return d + psi[c];
 }
 
@@ -253,7 +264,9 @@ int bbref_sim_create(const bbref_problem *p, const uint8_t *mat, bbref_sim **out
   for (int ax = 0; ax < 3; ++ax) {
     int N = ax == 0 ? s->nx : (ax == 1 ? s->ny : s->nz);
     s->pml_b[ax] = (double *)calloc((size_t)(2 * N + 2), sizeof(double));
-    for (int m = 0; m < 2 * N + 2; ++m) s->pml_b[ax][m] = pml_decay(s, ax, 0.5 * (m - 1));
+    s->pml_a[ax] = (double *)calloc((size_t)(2 * N + 2), sizeof(double));
+    for (int m = 0; m < 2 * N + 2; ++m)
+      pml_coeffs(s, ax, 0.5 * (m - 1), &s->pml_b[ax][m], &s->pml_a[ax][m]);
   }
   for (int f = 0; f < BBREF_NFIELDS; ++f) s->f[f] = (double *)calloc(n, sizeof(double));
   for (int f = 0; f < 9; ++f) {
@@ -270,7 +283,10 @@ void bbref_sim_destroy(bbref_sim *s) {
   free(s->rho); free(s->pi_u); free(s->mu_u); free(s->pi_tau); free(s->mu_tau);
   free(s->tau_s); free(s->mu);
   for (int f = 0; f < BBREF_NFIELDS; ++f) free(s->f[f]);
-  for (int ax = 0; ax < 3; ++ax) free(s->pml_b[ax]);
+  for (int ax = 0; ax < 3; ++ax) {
+    free(s->pml_b[ax]);
+    free(s->pml_a[ax]);
+  }
   for (int f = 0; f < 9; ++f) {
     free(s->psi_v[f]);
     free(s->psi_s[f]);
@@ -382,33 +398,36 @@ static void stress_update(bbref_sim *s) {
       }
 }
 
-/* Soft stress source on plane k_s at t = (n + 1/2) dt: the incident complex
-   pressure S (e^{+i omega t}) ramped in over two periods, scaled by 2 c_w dt/dx
-   so that each outgoing plane wave carries amplitude |S|. */
+/* Source (Section 2.3: the incident field enters as a stress source on a
+   plane perpendicular to the axis): a normal-traction jump of 2 S across the
+   plane z = (k_s + 1/2) dx, i.e. a force layer on the v_z faces there, applied
+   with the velocity update at t = n dt.  S is the incident complex pressure
+   (e^{+i omega t}) at that plane, ramped in over two periods; each side then
+   carries +-S for every angular component.  In the shear test mode the force
+   acts on v_x of plane k_s instead. */
 static void source_inject(bbref_sim *s, int n, const double *src) {
   if (!src) return;
   const double dt = s->info.dt, T = 2.0 * M_PI / s->info.omega;
-  double t = (n + 0.5) * dt;
+  double t = n * dt;
   double tr = 2.0 * T;
   double w = 1.0;
   if (t < tr) {
     double q = sin(M_PI * t / (2.0 * tr));
     w = q * q;
   }
-  double amp = dt * (2.0 * C_W / s->info.dx) * w;
   double cs = cos(s->info.omega * t), sn = sin(s->info.omega * t);
   int ks = s->info.source_k;
   for (int j = 0; j < s->ny; ++j)
     for (int i = 0; i < s->nx; ++i) {
       size_t q = (size_t)j * s->nx + i;
-      double dp = amp * (src[2 * q] * cs - src[2 * q + 1] * sn);
+      double force = 2.0 * w * (src[2 * q] * cs - src[2 * q + 1] * sn) / s->info.dx;
       size_t c = lin(s, i, j, ks);
       if (s->shear_src) {
-        s->f[BBREF_SXZ][c] -= dp;
+        double b = 2.0 / (s->rho[M(s, i, j, ks)] + s->rho[M(s, i + 1, j, ks)]);
+        s->f[BBREF_VX][c] += dt * b * force;
       } else {
-        s->f[BBREF_SXX][c] -= dp;
-        s->f[BBREF_SYY][c] -= dp;
-        s->f[BBREF_SZZ][c] -= dp;
+        double b = 2.0 / (s->rho[M(s, i, j, ks)] + s->rho[M(s, i, j, ks + 1)]);
+        s->f[BBREF_VZ][c] += dt * b * force;
       }
     }
 }
@@ -427,8 +446,8 @@ static void capture(bbref_sim *s) {
 
 void bbref_sim_step(bbref_sim *s, int32_t n, const double *src_re_im) {
   velocity_update(s);
-  stress_update(s);
   source_inject(s, n, src_re_im);
+  stress_update(s);
   if (n + 1 >= s->info.capture_start) capture(s);
 }
 

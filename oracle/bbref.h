@@ -28,7 +28,7 @@ extern "C" {
 
 /* Test modes (bit flags in bbref_problem.mode). */
 #define BBREF_LATERAL_PERIODIC 1 /* x and y wrap periodically, no x/y absorbing layer */
-#define BBREF_SOURCE_SHEAR_XZ 2  /* inject the source into sigma_xz instead of the normal stresses */
+#define BBREF_SOURCE_SHEAR_XZ 2  /* source force along x on the v_x of plane k_s (shear waves) */
 
 typedef struct {
   double rho, c_l, c_s, alpha_l, alpha_s; /* alpha in Np/m at the drive frequency */
@@ -69,7 +69,8 @@ int bbref_setup(const bbref_problem *p, bbref_info *info, bbref_matconst *mc);
 int bbref_sim_create(const bbref_problem *p, const uint8_t *mat, bbref_sim **out);
 void bbref_sim_destroy(bbref_sim *s);
 double *bbref_sim_field(bbref_sim *s, int32_t id); /* nz*ny*nx doubles, writable */
-/* Advance from t_n to t_{n+1}: velocity, stress+memory, source, capture. */
+/* Advance from t_n to t_{n+1}: velocity, source (force layer), stress+memory,
+   capture.  src_re_im: complex incident pressure at z = (k_s + 1/2) dx, [ny][nx]. */
 void bbref_sim_step(bbref_sim *s, int32_t n, const double *src_re_im);
 
 /* Whole solve: n_steps steps from rest, peak |p| map and its argmax over the

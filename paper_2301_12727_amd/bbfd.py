@@ -53,7 +53,9 @@ class PlanInfo(C.Structure):
 EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_material_constants", "bbfd_transducer_elements", "bbfd_source_rayleigh",
            "bbfd_solve", "bbfd_solve_direct", "bbfd_solve_profiled", "bbfd_status",
-           "bbfd_last_error"]
+           "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
+           "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
+           "bbfd_batch_status", "bbfd_batch_autotune"]
 
 _lib = None
 
@@ -74,11 +76,26 @@ def lib():
         L.bbfd_transducer_elements.argtypes = [vp, C.POINTER(Transducer), vp, C.c_int64,
                                                C.POINTER(C.c_int64)]
         L.bbfd_source_rayleigh.argtypes = [vp, C.POINTER(Transducer), vp, vp, C.c_uint64, vp]
+        L.bbfd_rayleigh_volume.argtypes = [vp, C.POINTER(Transducer), vp, vp, C.c_uint64, vp]
         L.bbfd_solve.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
         L.bbfd_solve_direct.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
         L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
         L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
         L.bbfd_last_error.restype = C.c_char_p
+        L.bbfd_batch_create.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(vp)]
+        L.bbfd_batch_destroy.argtypes = [vp]
+        L.bbfd_batch_destroy.restype = None
+        L.bbfd_batch_info.argtypes = [vp, C.POINTER(C.c_uint64), vp]
+        L.bbfd_batch_plan.argtypes = [vp, C.c_int32]
+        L.bbfd_batch_plan.restype = vp
+        L.bbfd_batch_offset.argtypes = [vp, C.c_int32]
+        L.bbfd_batch_offset.restype = C.c_uint64
+        L.bbfd_batch_set_shape.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.bbfd_batch_solve.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
+        L.bbfd_batch_status.argtypes = [vp, vp, C.c_int32, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_float), vp]
+        L.bbfd_batch_autotune.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, C.c_char_p,
+                                          C.c_int32, C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -169,6 +186,13 @@ class Plan:
                                           C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                           C.c_void_p(_stream(stream))))
 
+    def rayleigh_volume(self, t, field, ws, stream=None):
+        """Fill ``field`` (torch complex64 [nz, ny, nx], device) with the free field."""
+        ts = transducer_struct(t)
+        _check(lib().bbfd_rayleigh_volume(self.h, C.byref(ts), C.c_void_p(field.data_ptr()),
+                                          C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                          C.c_void_p(_stream(stream))))
+
     def solve(self, mat, src, peak, ws, stream=None, graph=True):
         """Enqueue a full solve (asynchronous)."""
         fn = lib().bbfd_solve if graph else lib().bbfd_solve_direct
@@ -194,6 +218,96 @@ class Plan:
         _check(lib().bbfd_status(self.h, C.c_void_p(ws.data_ptr()), C.byref(idx), C.byref(val),
                                  C.c_void_p(_stream(stream))))
         return int(idx.value), float(val.value)
+
+
+def _ptr_array(tensors):
+    return (C.c_void_p * len(tensors))(*[C.c_void_p(t.data_ptr()) for t in tensors])
+
+
+class Batch:
+    """Uneven sweep of independent solves run by one persistent captured graph."""
+
+    def __init__(self, cases, n_steps=None):
+        self._plans_py = [Plan.from_case(c, n_steps=n_steps) for c in cases]  # validation, info
+        probs = (Problem * len(cases))(*[p.problem for p in self._plans_py])
+        self._probs = probs
+        self.h = C.c_void_p()
+        _check(lib().bbfd_batch_create(probs, len(cases), C.byref(self.h)))
+        self.n = len(cases)
+        self.shapes = [p.shape for p in self._plans_py]
+
+    def close(self):
+        if self.h:
+            lib().bbfd_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        ws = C.c_uint64(0)
+        shape = (C.c_int32 * 4)()
+        _check(lib().bbfd_batch_info(self.h, C.byref(ws), shape))
+        return int(ws.value), tuple(shape)
+
+    @property
+    def workspace_bytes(self) -> int:
+        return self.info()[0]
+
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def source_rayleigh(self, i, t, src, ws, stream=None):
+        """Rayleigh plane of solve i, staged in solve i's part of the workspace."""
+        plan = lib().bbfd_batch_plan(self.h, i)
+        if not plan:
+            _check(EINVAL)
+        off = int(lib().bbfd_batch_offset(self.h, i))
+        sub = ws[off:]
+        ts = transducer_struct(t)
+        _check(lib().bbfd_source_rayleigh(C.c_void_p(plan), C.byref(ts),
+                                          C.c_void_p(src.data_ptr()), C.c_void_p(sub.data_ptr()),
+                                          sub.numel(), C.c_void_p(_stream(stream))))
+
+    def rayleigh_volume(self, i, t, field, ws, stream=None):
+        """Free field of solve i's transducer on its whole grid (complex64 [nz, ny, nx])."""
+        plan = lib().bbfd_batch_plan(self.h, i)
+        if not plan:
+            _check(EINVAL)
+        off = int(lib().bbfd_batch_offset(self.h, i))
+        sub = ws[off:]
+        ts = transducer_struct(t)
+        _check(lib().bbfd_rayleigh_volume(C.c_void_p(plan), C.byref(ts),
+                                          C.c_void_p(field.data_ptr()), C.c_void_p(sub.data_ptr()),
+                                          sub.numel(), C.c_void_p(_stream(stream))))
+
+    def set_shape(self, by, blocks, kchunk):
+        _check(lib().bbfd_batch_set_shape(self.h, by, blocks, kchunk))
+
+    def solve(self, mats, srcs, peaks, ws, stream=None):
+        self._keep = (_ptr_array(mats), _ptr_array(srcs), _ptr_array(peaks))
+        _check(lib().bbfd_batch_solve(self.h, *self._keep, C.c_void_p(ws.data_ptr()),
+                                      ws.numel(), C.c_void_p(_stream(stream))))
+
+    def status(self, ws, i, stream=None):
+        idx = C.c_int64(-1)
+        val = C.c_float(0.0)
+        _check(lib().bbfd_batch_status(self.h, C.c_void_p(ws.data_ptr()), i, C.byref(idx),
+                                       C.byref(val), C.c_void_p(_stream(stream))))
+        return int(idx.value), float(val.value)
+
+    def autotune(self, mats, srcs, peaks, ws, cache_path=None, probe_steps=10, stream=None):
+        arrs = (_ptr_array(mats), _ptr_array(srcs), _ptr_array(peaks))
+        best = C.c_double(0.0)
+        _check(lib().bbfd_batch_autotune(self.h, *arrs, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         C.c_void_p(_stream(stream)),
+                                         None if cache_path is None else cache_path.encode(),
+                                         probe_steps, C.byref(best)))
+        return float(best.value), self.info()[1]
 
 
 def run_case(case, n_steps=None, device="cuda", graph=True, **over):

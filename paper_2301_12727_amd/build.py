@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbbfd.so")
 
-SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip"]
+SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip", "surrogate.cpp", "nn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

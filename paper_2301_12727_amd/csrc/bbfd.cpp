@@ -10,8 +10,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
+#include <fstream>
 #include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -24,11 +27,16 @@ hipError_t launch_stress(const StepArgs &a, hipStream_t s);
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
                        hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
+hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, const Grid &g, int nseg,
+                           const float *lut, hipStream_t s);
 hipError_t launch_argmax(const float *P, int nx, int ny, int nz, int L, float *pv, long long *pi,
                          Status *st, hipStream_t s);
 int argmax_partials();
-hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, double dx, double z,
-                           double kw, double pre, float2 *out, hipStream_t s);
+hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, int planes, double dx,
+                           double z0, double kw, double pre, float2 *out, hipStream_t s);
+hipError_t launch_batched_step(int by, const StepArgs *desc, const BatchTile *tiles, int n_tiles,
+                               const float2 *coef, const int *cap, int max_steps, int n,
+                               int blocks, hipStream_t s);
 }  // namespace bbfd
 
 using namespace bbfd;
@@ -59,6 +67,15 @@ int hip_fail(hipError_t e, const char *what) {
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+}  // namespace
+
+namespace bbfd {
+// Shared error reporting for the other translation units of the library.
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace bbfd
+
+namespace {
+
 // Zener element relaxing at omega0 with strength tau: factor applied to rho c^2
 // so that the phase speed at omega0 equals the tabulated speed.
 double relaxed_factor(double tau) {
@@ -83,8 +100,9 @@ struct bbfd_plan {
   float relax_a = 0, relax_b = 0;
   std::vector<float> src_c, src_s;
   int kchunk = 1;
+  int nseg = 1;
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
-         off_state = 0, off_psi = 0, ws_bytes = 0;
+         off_cls = 0, off_state = 0, off_psi = 0, ws_bytes = 0;
   std::mutex mu;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -159,8 +177,10 @@ int validate_and_derive(const bbfd_problem *p, bbfd_plan *pl) {
   return BBFD_OK;
 }
 
-// CPML damping at coordinate xi (cells, integer or half-integer) along an axis
-// of n cells with an L-cell layer: quadratic profile, b = exp(-d dt), a = b - 1.
+// Frequency-shifted CPML at coordinate xi (cells, integer or half-integer)
+// along an axis of n cells with an L-cell layer: quadratic damping
+// d = d0 (l/L)^2 and shift alpha = pi f0 (1 - l/L) at depth l;
+// b = exp(-(d + alpha) dt), a = d/(d + alpha) (b - 1); b = 1, a = 0 outside.
 void pml_coeff(const bbfd_plan *pl, int n, double xi, float *b, float *a) {
   const int L = pl->prob.pml;
   double depth = 0.0;
@@ -171,8 +191,9 @@ void pml_coeff(const bbfd_plan *pl, int n, double xi, float *b, float *a) {
     return;
   }
   const double d = pl->d0 * (depth / L) * (depth / L);
-  *b = (float)std::exp(-d * pl->dt);
-  *a = (float)std::expm1(-d * pl->dt);
+  const double al = kPi * pl->prob.freq_hz * (1.0 - depth / L);
+  *b = (float)std::exp(-(d + al) * pl->dt);
+  *a = (float)(d / (d + al) * std::expm1(-(d + al) * pl->dt));
 }
 
 int build_tables(bbfd_plan *pl) {
@@ -190,6 +211,7 @@ int build_tables(bbfd_plan *pl) {
     o[kMuTau] = (float)(c[5] * c[3] * s);
     o[kTauS] = (float)c[3];
     o[kInvMu] = c[5] > 0 ? (float)(1.0 / (c[5] * s)) : INFINITY;
+    o[kLossless] = (c[5] == 0.0 && c[2] == 0.0) ? 1.0f : 0.0f;  // no shear, no P memory
   }
   const int dims[3] = {p.nx, p.ny, p.nz};
   float4 *t = pl->pmltab.data();
@@ -201,21 +223,22 @@ int build_tables(bbfd_plan *pl) {
   const double h = 0.5 * pl->omega * pl->dt;  // dt / (2 tau_sigma), tau_sigma = 1/omega0
   pl->relax_a = (float)((1.0 - h) / (1.0 + h));
   pl->relax_b = (float)(2.0 * h / (1.0 + h));
-  // Soft source per step, evaluated at t = (n + 1/2) dt: two-period sin^2 ramp,
-  // strength 2 c_w dt / dx so each outgoing wave carries |S|.
+  // Source: a normal-traction jump of 2 S across z = (ks + 1/2) dx, i.e. a
+  // force layer on the v_z faces there, applied with the velocity update of
+  // step n at t = n dt with a two-period sin^2 ramp.  In the scaled kernel
+  // variables the face gains b_z * (src_c Re S - src_s Im S).
   pl->src_c.resize(p.n_steps);
   pl->src_s.resize(p.n_steps);
   const double T = 1.0 / p.freq_hz;
   for (int n = 0; n < p.n_steps; ++n) {
-    const double t = (n + 0.5) * pl->dt;
+    const double t = n * pl->dt;
     double w = 1.0;
     if (t < 2.0 * T) {
       const double q = std::sin(kPi * t / (4.0 * T));
       w = q * q;
     }
-    const double amp = pl->dt * 2.0 * kCw / pl->dx * w;
-    pl->src_c[n] = (float)(amp * std::cos(pl->omega * t));
-    pl->src_s[n] = (float)(amp * std::sin(pl->omega * t));
+    pl->src_c[n] = (float)(2.0 * w * std::cos(pl->omega * t));
+    pl->src_s[n] = (float)(2.0 * w * std::sin(pl->omega * t));
   }
   return BBFD_OK;
 }
@@ -238,6 +261,8 @@ void layout(bbfd_plan *pl) {
   pl->off_pv = o; o += round_up(argmax_partials() * sizeof(float), 256);
   pl->off_pi = o; o += round_up(argmax_partials() * sizeof(long long), 256);
   pl->off_idx = o; o += round_up((size_t)g.stride, 256);
+  pl->nseg = (p.nx + kSeg - 1) / kSeg;
+  pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * p.nz, 256);
   pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
   pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
   pl->ws_bytes = o;
@@ -256,6 +281,8 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   StepArgs a{};
   a.g = pl->g;
   a.idx = (const uint8_t *)(ws + pl->off_idx);
+  a.cls = (const uint8_t *)(ws + pl->off_cls);
+  a.nseg = pl->nseg;
   a.lut = (const float *)(ws + pl->off_lut);
   const float4 *t = (const float4 *)(ws + pl->off_pml);
   a.pml.x = t;
@@ -295,10 +322,9 @@ int ensure_pinned(bbfd_plan *pl) {
   return BBFD_OK;
 }
 
-// Enqueue one whole solve on s (no synchronisation).  With ev != NULL (direct
-// launches only), ev[2n] / ev[2n+1] / ev[2n+2] bracket step n's two kernels.
-int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
-                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+// Per-solve prologue: tables, cleared state/peak/status, packed index map,
+// segment classes.
+int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char *ws, hipStream_t s) {
   const bbfd_problem &p = pl->prob;
   hipError_t e;
   if ((e = hipMemcpyAsync(ws + pl->off_lut, pl->h_lut, (size_t)p.n_materials * kLutW * sizeof(float),
@@ -319,6 +345,29 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
   if ((e = launch_pack(mat, (uint8_t *)(ws + pl->off_idx), pl->g, p.n_materials, &st->flags, s)) !=
       hipSuccess)
     return hip_fail(e, "index pack");
+  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_cls), pl->g,
+                           pl->nseg, (const float *)(ws + pl->off_lut), s)) != hipSuccess)
+    return hip_fail(e, "segment classes");
+  return BBFD_OK;
+}
+
+// Per-solve epilogue: peak voxel and finiteness into the status block.
+int enqueue_epilogue(const bbfd_plan *pl, float *peak, char *ws, hipStream_t s) {
+  const bbfd_problem &p = pl->prob;
+  hipError_t e = launch_argmax(peak, p.nx, p.ny, p.nz, p.pml, (float *)(ws + pl->off_pv),
+                               (long long *)(ws + pl->off_pi), (Status *)(ws + pl->off_status), s);
+  if (e != hipSuccess) return hip_fail(e, "argmax launch");
+  return BBFD_OK;
+}
+
+// Enqueue one whole solve on s (no synchronisation).  With ev != NULL (direct
+// launches only), ev[2n] / ev[2n+1] / ev[2n+2] bracket step n's two kernels.
+int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
+                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+  const bbfd_problem &p = pl->prob;
+  int rc = enqueue_prologue(pl, mat, peak, ws, s);
+  if (rc) return rc;
+  hipError_t e;
   StepArgs a = step_args(pl, mat, src, peak, ws);
   for (int n = 0; n < p.n_steps; ++n) {
     a.src_c = pl->src_c[n];
@@ -334,10 +383,7 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
     }
   }
   if (ev) (void)hipEventRecord(ev[2 * p.n_steps], s);
-  if ((e = launch_argmax(peak, p.nx, p.ny, p.nz, p.pml, (float *)(ws + pl->off_pv),
-                         (long long *)(ws + pl->off_pi), st, s)) != hipSuccess)
-    return hip_fail(e, "argmax launch");
-  return BBFD_OK;
+  return enqueue_epilogue(pl, peak, ws, s);
 }
 
 int check_solve_args(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
@@ -479,19 +525,21 @@ int bbfd_transducer_elements(const bbfd_plan *pl, const bbfd_transducer *t, doub
   return BBFD_OK;
 }
 
-int bbfd_source_rayleigh(const bbfd_plan *pl, const bbfd_transducer *t, float *src,
-                         void *workspace, uint64_t bytes, void *stream) {
-  if (!pl || !src) return fail(BBFD_EINVAL, "null argument");
+// Elements of t staged in the workspace, then the Rayleigh sum on `planes`
+// planes starting at z0 (cell-centre x, y).
+static int rayleigh_planes(const bbfd_plan *pl, const bbfd_transducer *t, float *out,
+                           void *workspace, uint64_t bytes, void *stream, int planes, double z0,
+                           double z_limit) {
+  if (!pl || !out) return fail(BBFD_EINVAL, "null argument");
   int rc = check_ws(pl, workspace, bytes);
   if (rc) return rc;
   std::vector<double> el;
   if ((rc = make_elements(t, pl->prob.freq_hz, el))) return rc;
   const size_t n = el.size() / 4;
-  const double zs = pl->ks * pl->dx;
   for (size_t e = 0; e < n; ++e)
-    if (!(el[4 * e + 2] < zs))
+    if (!(el[4 * e + 2] < z_limit))
       return fail(BBFD_EGEOMETRY, "transducer element %zu at z %.4g m is not before the source plane (%.4g m)",
-                  e, el[4 * e + 2], zs);
+                  e, el[4 * e + 2], z_limit);
   const size_t need = n * sizeof(double4);
   if (need > (size_t)kNState * pl->g.stride * sizeof(float))
     return fail(BBFD_ENOMEM, "too many elements (%zu) for the workspace", n);
@@ -503,9 +551,23 @@ int bbfd_source_rayleigh(const bbfd_plan *pl, const bbfd_transducer *t, float *s
   const double kw = pl->omega / kCw;
   const double pre = pl->omega * kRhoW * t->u0 / (2.0 * kPi);
   e = launch_rayleigh((const double4 *)(ws + pl->off_state), (int)n, pl->prob.nx, pl->prob.ny,
-                      pl->dx, zs, kw, pre, (float2 *)src, s);
+                      planes, pl->dx, z0, kw, pre, (float2 *)out, s);
   if (e != hipSuccess) return hip_fail(e, "rayleigh launch");
   return BBFD_OK;
+}
+
+int bbfd_source_rayleigh(const bbfd_plan *pl, const bbfd_transducer *t, float *src,
+                         void *workspace, uint64_t bytes, void *stream) {
+  if (!pl) return fail(BBFD_EINVAL, "null plan");
+  return rayleigh_planes(pl, t, src, workspace, bytes, stream, 1, (pl->ks + 0.5) * pl->dx,
+                         pl->ks * pl->dx);
+}
+
+int bbfd_rayleigh_volume(const bbfd_plan *pl, const bbfd_transducer *t, float *field,
+                         void *workspace, uint64_t bytes, void *stream) {
+  if (!pl) return fail(BBFD_EINVAL, "null plan");
+  return rayleigh_planes(pl, t, field, workspace, bytes, stream, pl->prob.nz, 0.0,
+                         pl->ks * pl->dx);
 }
 
 int bbfd_solve_direct(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float *peak,
@@ -611,6 +673,402 @@ int bbfd_status(const bbfd_plan *pl, const void *workspace, int64_t *peak_index,
   if (st.flags & kStatusIndex) return fail(BBFD_EINDEX, "material index >= n_materials in the map");
   if (st.flags & kStatusDiverged) return fail(BBFD_EDIVERGED, "non-finite peak pressure (diverged)");
   return BBFD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct bbfd_batch {
+  std::vector<bbfd_plan *> plans;
+  std::vector<int> order;       // solves by decreasing step count
+  std::vector<size_t> sub_off;  // per-solve workspace offset
+  size_t off_desc = 0, off_tiles = 0, off_coef = 0, off_cap = 0, ws_bytes = 0;
+  int max_steps = 0;
+  size_t max_tiles = 0;         // capacity of the tile table region
+  // launch shape (autotuned): rows per block, persistent blocks, z cells per tile
+  int by = 4, blocks = 1024, kchunk = 16;
+  std::vector<BatchTile> tiles;
+  std::vector<int> live;        // live tiles at each step (a prefix of tiles)
+  StepArgs *h_desc = nullptr;   // pinned staging, made at the first solve
+  BatchTile *h_tiles = nullptr;
+  float2 *h_coef = nullptr;
+  int *h_cap = nullptr;
+  std::mutex mu;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void *> key;
+  int key_shape[3] = {0, 0, 0};
+};
+
+namespace {
+
+// z cells per tile for a solve: the shape's kchunk, capped at nz.
+void build_tiles(bbfd_batch *b) {
+  b->tiles.clear();
+  std::vector<int> end_of_solve;
+  for (int s : b->order) {
+    const bbfd_problem &p = b->plans[s]->prob;
+    const int kc = std::max(1, std::min(b->kchunk, p.nz));
+    const int nbx = (p.nx + kSeg - 1) / kSeg, nby = (p.ny + b->by - 1) / b->by;
+    for (int k0 = 0; k0 < p.nz; k0 += kc)
+      for (int y = 0; y < nby; ++y)
+        for (int x = 0; x < nbx; ++x) {
+          BatchTile t{};
+          t.solve = s;
+          t.bx = x;
+          t.by = y;
+          t.k0 = k0;
+          t.k1 = std::min(k0 + kc, p.nz);
+          b->tiles.push_back(t);
+        }
+    end_of_solve.push_back((int)b->tiles.size());
+  }
+  b->live.assign(b->max_steps, 0);
+  for (int n = 0; n < b->max_steps; ++n) {
+    int live = 0;
+    for (size_t q = 0; q < b->order.size(); ++q)
+      if (b->plans[b->order[q]]->prob.n_steps > n) live = end_of_solve[q];
+    b->live[n] = live;
+  }
+}
+
+size_t tiles_capacity(const bbfd_batch *b) {
+  // the finest shape the tuner tries (1 row, 4 planes) bounds the table size
+  size_t n = 0;
+  for (const bbfd_plan *pl : b->plans) {
+    const bbfd_problem &p = pl->prob;
+    n += (size_t)((p.nx + kSeg - 1) / kSeg) * p.ny * ((p.nz + 3) / 4);
+  }
+  return n;
+}
+
+int batch_pinned(bbfd_batch *b) {
+  if (b->h_desc) return BBFD_OK;
+  const size_t n = b->plans.size();
+  hipError_t e;
+  if ((e = hipHostMalloc((void **)&b->h_desc, n * sizeof(StepArgs), hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(e, "pinned descriptor allocation");
+  if ((e = hipHostMalloc((void **)&b->h_tiles, b->max_tiles * sizeof(BatchTile), hipHostMallocDefault)) !=
+      hipSuccess)
+    return hip_fail(e, "pinned tile-table allocation");
+  if ((e = hipHostMalloc((void **)&b->h_coef, n * (size_t)b->max_steps * sizeof(float2),
+                         hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(e, "pinned coefficient allocation");
+  if ((e = hipHostMalloc((void **)&b->h_cap, n * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(e, "pinned capture allocation");
+  for (size_t s = 0; s < n; ++s) {
+    const bbfd_plan *pl = b->plans[s];
+    for (int k = 0; k < b->max_steps; ++k) {
+      const bool on = k < pl->prob.n_steps;
+      b->h_coef[s * b->max_steps + k] = make_float2(on ? pl->src_c[k] : 0.f, on ? pl->src_s[k] : 0.f);
+    }
+    b->h_cap[s] = pl->cap;
+  }
+  for (bbfd_plan *pl : b->plans) {
+    std::lock_guard<std::mutex> lock(pl->mu);
+    int rc = ensure_pinned(pl);
+    if (rc) return rc;
+  }
+  return BBFD_OK;
+}
+
+int check_batch_args(const bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
+                     float *const *peak, void *ws, uint64_t bytes) {
+  if (!b || !mat || !src || !peak) return fail(BBFD_EINVAL, "null argument");
+  for (size_t s = 0; s < b->plans.size(); ++s)
+    if (!mat[s] || !src[s] || !peak[s]) return fail(BBFD_EINVAL, "null device pointer for solve %zu", s);
+  if (!ws) return fail(BBFD_ENOMEM, "null workspace");
+  if ((uintptr_t)ws % 256) return fail(BBFD_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < b->ws_bytes)
+    return fail(BBFD_ENOMEM, "batch workspace of %llu bytes, need %llu", (unsigned long long)bytes,
+                (unsigned long long)b->ws_bytes);
+  return BBFD_OK;
+}
+
+// Descriptor and table uploads, every solve's prologue, `steps` batched steps
+// (all of them when steps < 0), every solve's epilogue (when complete).
+int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
+                  float *const *peak, char *ws, hipStream_t s, int steps = -1) {
+  const size_t n = b->plans.size();
+  for (size_t q = 0; q < n; ++q)
+    b->h_desc[q] = step_args(b->plans[q], mat[q], src[q], peak[q], ws + b->sub_off[q]);
+  std::copy(b->tiles.begin(), b->tiles.end(), b->h_tiles);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(ws + b->off_desc, b->h_desc, n * sizeof(StepArgs), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(ws + b->off_tiles, b->h_tiles, b->tiles.size() * sizeof(BatchTile),
+                          hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(ws + b->off_coef, b->h_coef, n * (size_t)b->max_steps * sizeof(float2),
+                          hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(ws + b->off_cap, b->h_cap, n * sizeof(int), hipMemcpyHostToDevice, s)))
+    return hip_fail(e, "batch table upload");
+  for (size_t q = 0; q < n; ++q) {
+    int rc = enqueue_prologue(b->plans[q], mat[q], peak[q], ws + b->sub_off[q], s);
+    if (rc) return rc;
+  }
+  const int last = steps < 0 ? b->max_steps : std::min(steps, b->max_steps);
+  for (int k = 0; k < last; ++k)
+    if ((e = launch_batched_step(b->by, (const StepArgs *)(ws + b->off_desc),
+                                 (const BatchTile *)(ws + b->off_tiles), b->live[k],
+                                 (const float2 *)(ws + b->off_coef), (const int *)(ws + b->off_cap),
+                                 b->max_steps, k, b->blocks, s)) != hipSuccess)
+      return hip_fail(e, "batched step launch");
+  if (steps >= 0) return BBFD_OK;
+  for (size_t q = 0; q < n; ++q) {
+    int rc = enqueue_epilogue(b->plans[q], peak[q], ws + b->sub_off[q], s);
+    if (rc) return rc;
+  }
+  return BBFD_OK;
+}
+
+void drop_graph(bbfd_batch *b) {
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  b->key.clear();
+}
+
+std::string batch_key(const bbfd_batch *b) {
+  // size class of the sweep: solve count, total cells (to 1 %) and the longest run
+  unsigned long long cells = 0;
+  for (const bbfd_plan *pl : b->plans) cells += (unsigned long long)pl->prob.nx * pl->prob.ny * pl->prob.nz;
+  double lg = std::log(std::max(1.0, (double)cells)) / std::log(1.01);
+  std::ostringstream os;
+  os << "gfx950:n" << b->plans.size() << ":c" << (long long)std::floor(lg) << ":s" << b->max_steps;
+  return os.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbfd_batch_create(const bbfd_problem *probs, int32_t n, bbfd_batch **out) {
+  if (!out) return fail(BBFD_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!probs || n <= 0) return fail(BBFD_EINVAL, "need at least one problem");
+  bbfd_batch *b = new (std::nothrow) bbfd_batch();
+  if (!b) return fail(BBFD_EINVAL, "out of host memory");
+  for (int s = 0; s < n; ++s) {
+    bbfd_plan *pl = nullptr;
+    int rc = bbfd_plan_create(&probs[s], &pl);
+    if (rc) {
+      std::string msg = g_err;
+      bbfd_batch_destroy(b);
+      return fail(rc, "problem %d: %s", s, msg.c_str());
+    }
+    b->plans.push_back(pl);
+    b->max_steps = std::max(b->max_steps, pl->prob.n_steps);
+  }
+  b->order.resize(n);
+  for (int s = 0; s < n; ++s) b->order[s] = s;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
+    return b->plans[a]->prob.n_steps > b->plans[c]->prob.n_steps;
+  });
+  b->max_tiles = tiles_capacity(b);
+  size_t o = 0;
+  b->off_desc = o; o += round_up((size_t)n * sizeof(StepArgs), 256);
+  b->off_tiles = o; o += round_up(b->max_tiles * sizeof(BatchTile), 256);
+  b->off_coef = o; o += round_up((size_t)n * b->max_steps * sizeof(float2), 256);
+  b->off_cap = o; o += round_up((size_t)n * sizeof(int), 256);
+  for (int s = 0; s < n; ++s) {
+    b->sub_off.push_back(o);
+    o += round_up(b->plans[s]->ws_bytes, 256);
+  }
+  b->ws_bytes = o;
+  build_tiles(b);
+  *out = b;
+  return BBFD_OK;
+}
+
+void bbfd_batch_destroy(bbfd_batch *b) {
+  if (!b) return;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->h_desc) (void)hipHostFree(b->h_desc);
+  if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+  if (b->h_coef) (void)hipHostFree(b->h_coef);
+  if (b->h_cap) (void)hipHostFree(b->h_cap);
+  for (bbfd_plan *pl : b->plans) bbfd_plan_destroy(pl);
+  delete b;
+}
+
+int bbfd_batch_info(const bbfd_batch *b, uint64_t *workspace_bytes, int32_t *shape) {
+  if (!b || !workspace_bytes) return fail(BBFD_EINVAL, "null argument");
+  *workspace_bytes = b->ws_bytes;
+  if (shape) {
+    shape[0] = b->by;
+    shape[1] = b->blocks;
+    shape[2] = b->kchunk;
+    shape[3] = (int32_t)b->tiles.size();
+  }
+  return BBFD_OK;
+}
+
+const bbfd_plan *bbfd_batch_plan(const bbfd_batch *b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->plans.size()) {
+    fail(BBFD_EINVAL, "solve index out of range");
+    return nullptr;
+  }
+  return b->plans[i];
+}
+
+uint64_t bbfd_batch_offset(const bbfd_batch *b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->plans.size()) return 0;
+  return b->sub_off[i];
+}
+
+int bbfd_batch_set_shape(bbfd_batch *b, int32_t by, int32_t blocks, int32_t kchunk) {
+  if (!b) return fail(BBFD_EINVAL, "null batch");
+  if (!(by == 1 || by == 2 || by == 4 || by == 8) || blocks < 1 || kchunk < 1)
+    return fail(BBFD_EINVAL, "bad launch shape (%d, %d, %d)", by, blocks, kchunk);
+  size_t ntiles = 0;
+  for (const bbfd_plan *pl : b->plans) {
+    const bbfd_problem &p = pl->prob;
+    const int kc = std::max(1, std::min((int)kchunk, p.nz));
+    ntiles += (size_t)((p.nx + kSeg - 1) / kSeg) * ((p.ny + by - 1) / by) * ((p.nz + kc - 1) / kc);
+  }
+  if (ntiles > b->max_tiles)
+    return fail(BBFD_EINVAL, "shape (%d, %d, %d) needs %zu tiles, table holds %zu", by, blocks, kchunk,
+                ntiles, b->max_tiles);
+  std::lock_guard<std::mutex> lock(b->mu);
+  b->by = by;
+  b->blocks = blocks;
+  b->kchunk = kchunk;
+  build_tiles(b);
+  drop_graph(b);
+  return BBFD_OK;
+}
+
+int bbfd_batch_solve(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
+                     float *const *peak, void *workspace, uint64_t bytes, void *stream) {
+  int rc = check_batch_args(b, mat, src, peak, workspace, bytes);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lock(b->mu);
+  if ((rc = batch_pinned(b))) return rc;
+  const size_t n = b->plans.size();
+  std::vector<const void *> key;
+  for (size_t q = 0; q < n; ++q) {
+    key.push_back(mat[q]);
+    key.push_back(src[q]);
+    key.push_back(peak[q]);
+  }
+  key.push_back(workspace);
+  const int shape[3] = {b->by, b->blocks, b->kchunk};
+  if (!b->exec || key != b->key || std::memcmp(shape, b->key_shape, sizeof shape) != 0) {
+    drop_graph(b);
+    hipError_t e;
+    if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "capture stream");
+    if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+      return hip_fail(e, "begin capture");
+    rc = enqueue_batch(b, mat, src, peak, (char *)workspace, b->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    b->graph = g;
+    if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+      b->exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    b->key = key;
+    std::memcpy(b->key_shape, shape, sizeof shape);
+  }
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return BBFD_OK;
+}
+
+int bbfd_batch_status(const bbfd_batch *b, const void *workspace, int32_t i, int64_t *peak_index,
+                      float *peak_value, void *stream) {
+  if (!b || i < 0 || i >= (int32_t)b->plans.size()) return fail(BBFD_EINVAL, "solve index out of range");
+  return bbfd_status(b->plans[i], (const char *)workspace + b->sub_off[i], peak_index, peak_value,
+                     stream);
+}
+
+int bbfd_batch_autotune(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
+                        float *const *peak, void *workspace, uint64_t bytes, void *stream,
+                        const char *cache_path, int32_t probe_steps, double *best_ms) {
+  int rc = check_batch_args(b, mat, src, peak, workspace, bytes);
+  if (rc) return rc;
+  const std::string key = batch_key(b);
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      int by, blocks, kc;
+      double ms;
+      if ((ls >> k >> by >> blocks >> kc >> ms) && k == key) {
+        if (best_ms) *best_ms = ms;
+        return bbfd_batch_set_shape(b, by, blocks, kc);
+      }
+    }
+  }
+  if (probe_steps < 1) probe_steps = 1;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(BBFD_EHIP, "event create");
+  double best = 1e300;
+  int bb_ = b->by, bl_ = b->blocks, kc_ = b->kchunk;
+  const int bys[] = {1, 2, 4, 8};
+  const int kcs[] = {4, 8, 16, 32, 64};
+  const int bls[] = {512, 1024, 2048, 4096};
+  {
+    std::lock_guard<std::mutex> lock(b->mu);
+    if ((rc = batch_pinned(b))) goto done;
+  }
+  for (int by : bys)
+    for (int kc : kcs)
+      for (int bl : bls) {
+        if ((rc = bbfd_batch_set_shape(b, by, bl, kc))) {
+          rc = BBFD_OK;  // shape not representable: skip it
+          continue;
+        }
+        std::lock_guard<std::mutex> lock(b->mu);
+        // warm-up pass (prologue + probe steps), then the timed probe steps
+        if ((rc = enqueue_batch(b, mat, src, peak, (char *)workspace, s, probe_steps))) goto done;
+        (void)hipEventRecord(e0, s);
+        for (int k = 0; k < probe_steps; ++k) {
+          hipError_t e = launch_batched_step(b->by, (const StepArgs *)((char *)workspace + b->off_desc),
+                                             (const BatchTile *)((char *)workspace + b->off_tiles),
+                                             b->live[k], (const float2 *)((char *)workspace + b->off_coef),
+                                             (const int *)((char *)workspace + b->off_cap), b->max_steps, k,
+                                             b->blocks, s);
+          if (e != hipSuccess) {
+            rc = hip_fail(e, "tuning launch");
+            goto done;
+          }
+        }
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(BBFD_EHIP, "tuning sync");
+          goto done;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          bb_ = by;
+          bl_ = bl;
+          kc_ = kc;
+        }
+      }
+  rc = bbfd_batch_set_shape(b, bb_, bl_, kc_);
+  if (rc == BBFD_OK && best_ms) *best_ms = best;
+  if (rc == BBFD_OK && cache_path && *cache_path) {
+    std::ofstream outf(cache_path, std::ios::app);
+    outf << key << " " << bb_ << " " << bl_ << " " << kc_ << " " << best << "\n";
+  }
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 }  // extern "C"

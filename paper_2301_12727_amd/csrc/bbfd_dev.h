@@ -37,8 +37,17 @@ enum LutField {
   kMuTau = 4,  // mu_R * tau_S * dt / dx  (memory-variable target, shear part)
   kTauS = 5,   // tau_S                   (edge average)
   kInvMu = 6,  // dx / (mu_R * dt), +inf for fluids (edge harmonic mean)
+  kLossless = 7,  // 1 for a fluid without attenuation (no shear, no memory), else 0
   kLutW = 8
 };
+
+// Row segments: the kernels' waves cover 64 consecutive x cells of one row.
+// A segment's class is m + 1 when every cell within two cells of it (the
+// reach of both stencils, ghosts included) holds the same lossless fluid m;
+// then shear stresses and memory variables there stay exactly zero and the
+// three normal stresses stay equal, so the wave takes the acoustic path.
+// Class 0 (mixed) takes the full viscoelastic path.
+constexpr int kSeg = 64;
 
 // State array slots inside the workspace.
 enum Field {
@@ -50,7 +59,8 @@ constexpr int kNPsi = 18;
 
 // CPML coefficient table per axis: 4 floats per index
 //   [b at integer position, a at integer, b at half position i+1/2, a at half]
-// with b = exp(-d dt), a = b - 1; b = 1, a = 0 where the profile is zero.
+// with b = exp(-(d + alpha) dt), a = d/(d + alpha) (b - 1) (frequency-shifted
+// CPML); b = 1, a = 0 where the profile is zero.
 struct PmlTab {
   const float4 *x, *y, *z;
 };
@@ -58,6 +68,8 @@ struct PmlTab {
 struct StepArgs {
   Grid g;
   const uint8_t *idx;     // padded, replicated ghosts
+  const uint8_t *cls;     // [nz][ny][nseg] segment classes
+  int nseg;               // ceil(nx / kSeg)
   const float *lut;       // kLutW floats per material
   PmlTab pml;
   float *f[kNState];      // padded state arrays
@@ -66,9 +78,18 @@ struct StepArgs {
   float *peak;            // [nz][ny][nx]
   float relax_a;          // (1 - h) / (1 + h), h = omega dt / 2
   float relax_b;          // 2 h / (1 + h)
-  float src_c, src_s;     // per step: dp = src_c * Re S - src_s * Im S
+  float src_c, src_s;     // per step: v_z face force src_c * Re S - src_s * Im S (x b_z)
   int capture;            // 1: update the peak map after this step
   int kchunk;             // z cells per block
+};
+
+// Batched sweeps: one entry per (solve, tile); solves are ordered by
+// decreasing step count so the live tiles of step n are a prefix of the table.
+struct BatchTile {
+  int solve;
+  int bx, by;   // x segment and row-block index inside the solve
+  int k0, k1;   // z range
+  int pad[3];
 };
 
 // Device status block at the front of the workspace.

@@ -1,9 +1,10 @@
 // Viscoelastic FDTD step kernels for gfx950 (BabelBrain Section 2.3, Eq. 1).
 //
 // One time step is two launches:
-//   k_velocity : v^{n-1/2} -> v^{n+1/2}   (Eq. 1 rows 1-3)
-//   k_stress   : sigma^n -> sigma^{n+1}, Zener memory variables, soft source
-//                on plane ks, peak |p| capture (Eq. 1 rows 4-9, Section 3.2)
+//   k_velocity : v^{n-1/2} -> v^{n+1/2} (Eq. 1 rows 1-3) and the source force
+//                on the v_z faces of plane ks (Section 2.3)
+//   k_stress   : sigma^n -> sigma^{n+1}, Zener memory variables, peak |p|
+//                capture (Eq. 1 rows 4-9, Section 3.2)
 // Both are HBM-bandwidth bound stencils.  A block is a 64x4 x-y tile of
 // columns marching over a chunk of z; x is the fastest (coalesced) axis.  The
 // absorbing layer (CPML) is applied per cell behind a slab test that is uniform
@@ -27,13 +28,16 @@ __device__ __forceinline__ float cpml(float *psi, long long c, float b, float a,
 
 __device__ __forceinline__ bool in_layer(int i, int n, int L) { return i < L || i >= n - L; }
 
-__global__ void __launch_bounds__(256) k_velocity(StepArgs A) {
+// Velocity update (Eq. 1 rows 1-3) of one tile: x segment bx (one cell per
+// lane), rows by * blockDim.y + threadIdx.y, planes [k0, k1).  On plane ks the
+// v_z faces also receive the source force (src_c Re S - src_s Im S, scaled by
+// the face buoyancy): a normal-traction jump of 2 S across z = (ks + 1/2) dx.
+__device__ __forceinline__ void velocity_tile(const StepArgs &A, int bx, int by, int k0, int k1,
+                                              float src_c, float src_s) {
   const Grid g = A.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int i = bx * kSeg + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  const int k0 = blockIdx.z * A.kchunk;
-  const int k1 = min(k0 + A.kchunk, g.nz);
   const long long P = g.pitch, PL = g.plane;
   const float *__restrict__ sxx = A.f[SXX], *__restrict__ syy = A.f[SYY];
   const float *__restrict__ szz = A.f[SZZ], *__restrict__ sxy = A.f[SXY];
@@ -44,8 +48,28 @@ __global__ void __launch_bounds__(256) k_velocity(StepArgs A) {
   const bool px = in_layer(i, g.nx, g.L), py = in_layer(j, g.ny, g.L);
   const float4 tx = px ? A.pml.x[i] : make_float4(1.f, 0.f, 1.f, 0.f);
   const float4 ty = py ? A.pml.y[j] : make_float4(1.f, 0.f, 1.f, 0.f);
+  const int seg = bx;  // blockDim.x == kSeg: one wave = one row segment
   for (int k = k0; k < k1; ++k) {
     const long long c = g.off(i, j, k);
+    const bool pz = in_layer(k, g.nz, g.L);
+    const int cl = __builtin_amdgcn_readfirstlane(A.cls[((long long)k * g.ny + j) * A.nseg + seg]);
+    if (cl) {
+      // acoustic path: the three normal stresses are equal and the shear
+      // stresses vanish throughout the stencil's reach
+      const float b = 1.f / lut[(cl - 1) * kLutW + kRhoS];
+      float d1 = DP(sxx, c, 1), e2 = DP(sxx, c, P), f3 = DP(sxx, c, PL);
+      if (px) d1 = cpml(A.psi[0], c, tx.z, tx.w, d1);
+      if (py) e2 = cpml(A.psi[4], c, ty.z, ty.w, e2);
+      if (pz) f3 = cpml(A.psi[8], c, A.pml.z[k].z, A.pml.z[k].w, f3);
+      vx[c] += b * d1;
+      vy[c] += b * e2;
+      if (k == g.ks) {
+        const float2 q = A.src[(long long)j * g.nx + i];
+        f3 += src_c * q.x - src_s * q.y;
+      }
+      vz[c] += b * f3;
+      continue;
+    }
     const float r0 = lut[idx[c] * kLutW + kRhoS];
     const float bx = 2.f / (r0 + lut[idx[c + 1] * kLutW + kRhoS]);
     const float by = 2.f / (r0 + lut[idx[c + P] * kLutW + kRhoS]);
@@ -53,7 +77,6 @@ __global__ void __launch_bounds__(256) k_velocity(StepArgs A) {
     float d1 = DP(sxx, c, 1), d2 = DM(sxy, c, P), d3 = DM(sxz, c, PL);
     float e1 = DM(sxy, c, 1), e2 = DP(syy, c, P), e3 = DM(syz, c, PL);
     float f1 = DM(sxz, c, 1), f2 = DM(syz, c, P), f3 = DP(szz, c, PL);
-    const bool pz = in_layer(k, g.nz, g.L);
     if (px) {
       d1 = cpml(A.psi[0], c, tx.z, tx.w, d1);
       e1 = cpml(A.psi[3], c, tx.x, tx.y, e1);
@@ -72,7 +95,12 @@ __global__ void __launch_bounds__(256) k_velocity(StepArgs A) {
     }
     vx[c] += bx * (d1 + d2 + d3);
     vy[c] += by * (e1 + e2 + e3);
-    vz[c] += bz * (f1 + f2 + f3);
+    float fz = f1 + f2 + f3;
+    if (k == g.ks) {  // traction source: force layer on the v_z faces of plane ks
+      const float2 q = A.src[(long long)j * g.nx + i];
+      fz += src_c * q.x - src_s * q.y;
+    }
+    vz[c] += bz * fz;
   }
 }
 
@@ -96,13 +124,14 @@ __device__ __forceinline__ void edge(float &s, float &r, float e, const float *l
   zener(s, r, mue * (1.f + te) * e, mue * te * e, ra, rb);
 }
 
-__global__ void __launch_bounds__(256) k_stress(StepArgs A) {
+// Stress + memory update (Eq. 1 rows 4-9) and peak capture of one tile;
+// capture is this step's flag.
+__device__ __forceinline__ void stress_tile(const StepArgs &A, int bx, int by, int k0, int k1,
+                                            int capture) {
   const Grid g = A.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int i = bx * kSeg + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  const int k0 = blockIdx.z * A.kchunk;
-  const int k1 = min(k0 + A.kchunk, g.nz);
   const long long P = g.pitch, PL = g.plane;
   const float *__restrict__ vx = A.f[VX], *__restrict__ vy = A.f[VY], *__restrict__ vz = A.f[VZ];
   float *__restrict__ sxxp = A.f[SXX], *__restrict__ syyp = A.f[SYY], *__restrict__ szzp = A.f[SZZ];
@@ -115,13 +144,33 @@ __global__ void __launch_bounds__(256) k_stress(StepArgs A) {
   const bool px = in_layer(i, g.nx, g.L), py = in_layer(j, g.ny, g.L);
   const float4 tx = px ? A.pml.x[i] : make_float4(1.f, 0.f, 1.f, 0.f);
   const float4 ty = py ? A.pml.y[j] : make_float4(1.f, 0.f, 1.f, 0.f);
+  const int seg = bx;
   for (int k = k0; k < k1; ++k) {
     const long long c = g.off(i, j, k);
+    const bool pz = in_layer(k, g.nz, g.L);
+    const int cl = __builtin_amdgcn_readfirstlane(A.cls[((long long)k * g.ny + j) * A.nseg + seg]);
+    if (cl) {
+      // acoustic path: only the (equal) normal stresses change
+      float exx = DM(vx, c, 1), eyy = DM(vy, c, P), ezz = DM(vz, c, PL);
+      if (px) exx = cpml(A.psi[9], c, tx.x, tx.y, exx);
+      if (py) eyy = cpml(A.psi[10], c, ty.x, ty.y, eyy);
+      if (pz) ezz = cpml(A.psi[11], c, A.pml.z[k].x, A.pml.z[k].y, ezz);
+      const float sn = sxxp[c] + lut[(cl - 1) * kLutW + kPiU] * (exx + eyy + ezz);
+      sxxp[c] = sn;
+      syyp[c] = sn;
+      szzp[c] = sn;
+      if (capture) {
+        const long long q = ((long long)k * g.ny + j) * g.nx + i;
+        const float a = fabsf(sn + sn + sn) / 3.f;
+        const float p = A.peak[q];
+        if (a > p || a != a) A.peak[q] = a;
+      }
+      continue;
+    }
     float exx = DM(vx, c, 1), eyy = DM(vy, c, P), ezz = DM(vz, c, PL);
     float dyvx = DP(vx, c, P), dxvy = DP(vy, c, 1);
     float dzvx = DP(vx, c, PL), dxvz = DP(vz, c, 1);
     float dzvy = DP(vy, c, PL), dyvz = DP(vz, c, P);
-    const bool pz = in_layer(k, g.nz, g.L);
     if (px) {
       exx = cpml(A.psi[9], c, tx.x, tx.y, exx);
       dxvy = cpml(A.psi[13], c, tx.z, tx.w, dxvy);
@@ -159,23 +208,50 @@ __global__ void __launch_bounds__(256) k_stress(StepArgs A) {
     edge(sxy, rxy, dyvx + dxvy, lut, m0, mx, my, mxy, ra, rb);
     edge(sxz, rxz, dzvx + dxvz, lut, m0, mx, mz, mxz, ra, rb);
     edge(syz, ryz, dzvy + dyvz, lut, m0, my, mz, myz, ra, rb);
-    if (k == g.ks) {
-      const float2 s = A.src[(long long)j * g.nx + i];
-      const float dp = A.src_c * s.x - A.src_s * s.y;
-      sxx -= dp;
-      syy -= dp;
-      szz -= dp;
-    }
     sxxp[c] = sxx; syyp[c] = syy; szzp[c] = szz;
     rxxp[c] = rxx; ryyp[c] = ryy; rzzp[c] = rzz;
     sxyp[c] = sxy; sxzp[c] = sxz; syzp[c] = syz;
     rxyp[c] = rxy; rxzp[c] = rxz; ryzp[c] = ryz;
-    if (A.capture) {
+    if (capture) {
       const long long q = ((long long)k * g.ny + j) * g.nx + i;
       const float a = fabsf(sxx + syy + szz) / 3.f;
       const float p = A.peak[q];
       if (a > p || a != a) A.peak[q] = a;
     }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_velocity(StepArgs A) {
+  const int k0 = blockIdx.z * A.kchunk;
+  velocity_tile(A, blockIdx.x, blockIdx.y, k0, min(k0 + A.kchunk, A.g.nz), A.src_c, A.src_s);
+}
+
+__global__ void __launch_bounds__(256) k_stress(StepArgs A) {
+  const int k0 = blockIdx.z * A.kchunk;
+  stress_tile(A, blockIdx.x, blockIdx.y, k0, min(k0 + A.kchunk, A.g.nz), A.capture);
+}
+
+// Persistent batched step kernels: a fixed grid walks the live prefix of the
+// (solve, tile) table; every solve keeps its own grid, tables, step count and
+// source coefficients.  The per-cell arithmetic is the single-solve tile code.
+template <int BY>
+__global__ void __launch_bounds__(kSeg * BY)
+    k_velocity_batched(const StepArgs *__restrict__ desc, const BatchTile *__restrict__ tiles,
+                       int n_tiles, const float2 *__restrict__ coef, int max_steps, int n) {
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    const float2 cs = coef[(long long)tl.solve * max_steps + n];
+    velocity_tile(desc[tl.solve], tl.bx, tl.by, tl.k0, tl.k1, cs.x, cs.y);
+  }
+}
+
+template <int BY>
+__global__ void __launch_bounds__(kSeg * BY)
+    k_stress_batched(const StepArgs *__restrict__ desc, const BatchTile *__restrict__ tiles,
+                     int n_tiles, const int *__restrict__ cap, int n) {
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const BatchTile tl = tiles[t];
+    stress_tile(desc[tl.solve], tl.bx, tl.by, tl.k0, tl.k1, (n + 1 >= cap[tl.solve]) ? 1 : 0);
   }
 }
 
@@ -196,6 +272,34 @@ __global__ void k_pack_idx(const uint8_t *__restrict__ mat, uint8_t *__restrict_
       m = 0;
     }
     idx[kX0 - kGhost + t] = (uint8_t)m;
+  }
+}
+
+// Segment classes (see kSeg): m + 1 if every cell within two cells of the
+// segment holds lossless fluid m, else 0.  Reads the padded, ghost-replicated
+// index map, so cells outside the grid count as their edge neighbour.
+__global__ void k_classify(const uint8_t *__restrict__ idx, uint8_t *__restrict__ cls, Grid g,
+                           int nseg, const float *__restrict__ lut) {
+  const long long total = (long long)nseg * g.ny * g.nz;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int sg = (int)(t % nseg);
+    const long long r = t / nseg;
+    const int j = (int)(r % g.ny), k = (int)(r / g.ny);
+    const int x0 = sg * kSeg;
+    const int xa = x0 - kGhost, xb = min(x0 + kSeg - 1, g.nx - 1) + kGhost;
+    const int m = idx[g.off(x0, j, k)];
+    bool ok = m < 255 && lut[m * kLutW + kLossless] != 0.f;
+    for (int dk = -kGhost; ok && dk <= kGhost; ++dk)
+      for (int dj = -kGhost; ok && dj <= kGhost; ++dj) {
+        const uint8_t *row = idx + g.off(0, j + dj, k + dk);
+        for (int x = xa; x <= xb; ++x)
+          if (row[x] != m) {
+            ok = false;
+            break;
+          }
+      }
+    cls[t] = ok ? (uint8_t)(m + 1) : (uint8_t)0;
   }
 }
 
@@ -305,7 +409,7 @@ __global__ void __launch_bounds__(kRedThreads)
 
 // ------------------------------------------------------------------ launchers
 
-static constexpr int kBX = 64, kBY = 4;
+static constexpr int kBX = kSeg, kBY = 4;
 
 static dim3 step_grid(const StepArgs &a) {
   return dim3((a.g.nx + kBX - 1) / kBX, (a.g.ny + kBY - 1) / kBY,
@@ -334,6 +438,12 @@ hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_ma
   return hipGetLastError();
 }
 
+hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, const Grid &g, int nseg,
+                           const float *lut, hipStream_t s) {
+  hipLaunchKernelGGL(k_classify, dim3(4096), dim3(256), 0, s, idx, cls, g, nseg, lut);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s) {
   const long long n4 = ((uintptr_t)p % 16 == 0) ? n / 4 : 0;
   if (n4 > 0) {
@@ -348,6 +458,30 @@ hipError_t launch_fill(float *p, long long n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_tail, dim3((unsigned)blocks), dim3(256), 0, s, p + 4 * n4, rest, v);
   }
   return hipGetLastError();
+}
+
+template <int BY>
+static hipError_t batched_step(const StepArgs *desc, const BatchTile *tiles, int n_tiles,
+                               const float2 *coef, const int *cap, int max_steps, int n,
+                               int blocks, hipStream_t s) {
+  const dim3 grid(min(blocks, n_tiles)), block(kSeg, BY, 1);
+  hipLaunchKernelGGL(k_velocity_batched<BY>, grid, block, 0, s, desc, tiles, n_tiles, coef,
+                     max_steps, n);
+  hipLaunchKernelGGL(k_stress_batched<BY>, grid, block, 0, s, desc, tiles, n_tiles, cap, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_step(int by, const StepArgs *desc, const BatchTile *tiles, int n_tiles,
+                               const float2 *coef, const int *cap, int max_steps, int n,
+                               int blocks, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (by) {
+    case 1: return batched_step<1>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, s);
+    case 2: return batched_step<2>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, s);
+    case 4: return batched_step<4>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, s);
+    case 8: return batched_step<8>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 int argmax_partials() { return kRedBlocks; }

@@ -12,14 +12,16 @@ namespace bbfd {
 
 constexpr int kRayThreads = 256;
 
+// blockIdx.y selects the plane z = z0 + blockIdx.y * dx; out is [planes][ny][nx].
 __global__ void __launch_bounds__(kRayThreads)
-    k_rayleigh(const double4 *__restrict__ el, int n_el, int nx, int ny, double dx, double z,
+    k_rayleigh(const double4 *__restrict__ el, int n_el, int nx, int ny, double dx, double z0,
                double kw, double pre, float2 *__restrict__ out) {
   __shared__ double4 tile[kRayThreads];
   const int q = blockIdx.x * kRayThreads + threadIdx.x;
   const bool live = q < nx * ny;
   const int i = live ? q % nx : 0, j = live ? q / nx : 0;
-  const double x = i * dx, y = j * dx;
+  const double x = i * dx, y = j * dx, z = z0 + blockIdx.y * dx;
+  out += (long long)blockIdx.y * nx * ny;
   const double two_pi = 6.283185307179586476925286766559;
   double sr = 0.0, si = 0.0;
   for (int t0 = 0; t0 < n_el; t0 += kRayThreads) {
@@ -44,11 +46,11 @@ __global__ void __launch_bounds__(kRayThreads)
   if (live) out[q] = make_float2((float)(pre * sr), (float)(pre * si));
 }
 
-hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, double dx, double z,
-                           double kw, double pre, float2 *out, hipStream_t s) {
+hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, int planes, double dx,
+                           double z0, double kw, double pre, float2 *out, hipStream_t s) {
   const int blocks = (nx * ny + kRayThreads - 1) / kRayThreads;
-  hipLaunchKernelGGL(k_rayleigh, dim3(blocks), dim3(kRayThreads), 0, s, el, n_el, nx, ny, dx, z,
-                     kw, pre, out);
+  hipLaunchKernelGGL(k_rayleigh, dim3(blocks, planes), dim3(kRayThreads), 0, s, el, n_el, nx, ny,
+                     dx, z0, kw, pre, out);
   return hipGetLastError();
 }
 

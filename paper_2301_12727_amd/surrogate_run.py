@@ -1,0 +1,299 @@
+"""Learned-surrogate workflow on top of libbbfd: FDTD-generated training data,
+training with the library's kernels, held-out evaluation against FDTD, the
+out-of-distribution fallback to FDTD, and throughput.
+
+Data: n^3 skull patches (``synth.surrogate_case``), solved by the batched
+FDTD path.  Inputs per sample (built by the library's feature kernel):
+c/c_w - 1, rho/rho_w - 1, and the cosine/sine of the phase of the
+transducer's free field in water (Rayleigh integral over the whole grid).
+Target: log of the peak-pressure map over the free field's peak, clipped at
+1e-3 (the network learns the transmission loss and aberration).
+
+Focal error of a sample: |max P_hat - max P| / max P over the post-skull
+region (cells deeper than the last bone cell of their own column, outside the
+absorbing layer); focal distance: voxel distance between the two maxima.
+No-learning baseline: the free field scaled by the training-mean ratio of
+post-skull peaks (FDTD over free field).
+
+Run: python -m paper_2301_12727_amd.surrogate_run --out results.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import bbfd as bb
+from . import surrogate as sg
+
+P_FLOOR = 1e-3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _synth():
+    import synth
+    return synth
+
+
+def post_skull_mask(mat: np.ndarray, pml: int) -> np.ndarray:
+    """Cells deeper than the last bone cell of their (i, j) column, outside the layer."""
+    nz = mat.shape[0]
+    bone = mat > 0
+    k = np.arange(nz)[:, None, None]
+    last = np.where(bone.any(axis=0), (np.where(bone, k, -1)).max(axis=0), -1)
+    m = k > last[None]
+    m[:pml] = False
+    m[nz - pml:] = False
+    m[:, :pml] = False
+    m[:, -pml:] = False
+    m[:, :, :pml] = False
+    m[:, :, -pml:] = False
+    return m
+
+
+def ood_stats(case) -> dict:
+    m = case.mat
+    return {"freq_hz": float(case.freq_hz), "bone_frac": float((m > 0).mean()),
+            "trab_frac": float((m > 1).mean() / max((m > 0).mean(), 1e-12)),
+            "max_index": int(m.max())}
+
+
+class Dataset:
+    """Inputs, targets and per-sample metadata resident on the GPU."""
+
+    def __init__(self, n, count, device):
+        import torch
+        self.n = n
+        self.x = torch.empty((count, 4, n, n, n), dtype=torch.float32, device=device)
+        self.y = torch.empty((count, 1, n, n, n), dtype=torch.float32, device=device)
+        self.pref = np.zeros(count)
+        self.peak_post = np.zeros(count)
+        self.free_post = np.zeros(count)
+        self.argmax_post = np.zeros((count, 3), dtype=np.int64)
+        self.masks = []
+        self.stats = []
+        self.free_abs = []
+
+
+def generate(seeds, n=64, device="cuda", chunk=32, keep_masks=False) -> Dataset:
+    """FDTD-solve the surrogate cases of ``seeds`` (batched) and build the
+    network inputs and targets on the GPU."""
+    import torch
+    synth = _synth()
+    ds = Dataset(n, len(seeds), device)
+    t0 = time.time()
+    for c0 in range(0, len(seeds), chunk):
+        cases = [synth.surrogate_case(s, n) for s in seeds[c0:c0 + chunk]]
+        b = bb.Batch(cases)
+        ws = b.workspace(device)
+        mats = [torch.from_numpy(c.mat).to(device) for c in cases]
+        srcs = [torch.empty((n, n), dtype=torch.complex64, device=device) for _ in cases]
+        peaks = [torch.empty((n, n, n), dtype=torch.float32, device=device) for _ in cases]
+        free = torch.empty((n, n, n), dtype=torch.complex64, device=device)
+        for i, c in enumerate(cases):
+            b.source_rayleigh(i, c.transducer, srcs[i], ws)
+        b.solve(mats, srcs, peaks, ws)
+        for i, c in enumerate(cases):
+            b.status(ws, i)
+            q = c0 + i
+            b.rayleigh_volume(i, c.transducer, free, ws)
+            table = np.zeros((c.materials.shape[0], 2), dtype=np.float32)
+            table[:, 0] = c.materials[:, 1] / synth.C_WATER - 1.0
+            table[:, 1] = c.materials[:, 0] / synth.RHO_WATER - 1.0
+            sg.features(mats[i], torch.from_numpy(table).to(device), free, ds.x[q])
+            fa = free.abs()
+            ks = c.pml
+            pref = float(fa[ks:n - c.pml, c.pml:n - c.pml, c.pml:n - c.pml].max())
+            ds.pref[q] = pref
+            ds.y[q, 0] = torch.log(torch.clamp(peaks[i] / pref, min=P_FLOOR))
+            mask = post_skull_mask(c.mat, c.pml)
+            P = peaks[i].cpu().numpy()
+            Fa = fa.cpu().numpy()
+            Pm = np.where(mask, P, -1.0)
+            ds.peak_post[q] = Pm.max()
+            ds.argmax_post[q] = np.unravel_index(Pm.argmax(), Pm.shape)
+            ds.free_post[q] = np.where(mask, Fa, -1.0).max()
+            ds.stats.append(ood_stats(c))
+            if keep_masks:
+                ds.masks.append(mask)
+                ds.free_abs.append(Fa)
+        del b, ws
+        torch.cuda.empty_cache()
+        log(f"[surrogate] generated {min(c0 + chunk, len(seeds))}/{len(seeds)} ({time.time() - t0:.1f}s)")
+    return ds
+
+
+def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epochs=1000):
+    """Adam on the mean squared error of the log target, cosine-decayed
+    learning rate over a time budget.  Returns (params, loss history)."""
+    import torch
+    params = model.init_params(seed)
+    st = model.train_state(params)
+    rng = np.random.default_rng(seed)
+    N = ds.x.shape[0]
+    hist = []
+    t0 = time.time()
+    steps_per_epoch = N // batch
+    epoch = 0
+    while time.time() - t0 < seconds and epoch < max_epochs:
+        order = rng.permutation(N)
+        acc = 0.0
+        for s in range(steps_per_epoch):
+            frac = min(1.0, (time.time() - t0) / seconds)
+            lr_t = 1e-5 + 0.5 * (lr - 1e-5) * (1 + math.cos(math.pi * frac))
+            idx = torch.from_numpy(order[s * batch:(s + 1) * batch]).to(ds.x.device)
+            loss = model.train_step(st, ds.x.index_select(0, idx), ds.y.index_select(0, idx),
+                                    lr=lr_t, sync=(s % 50 == 0))
+            if loss is not None:
+                acc = loss
+        epoch += 1
+        hist.append({"epoch": epoch, "loss": acc, "t": round(time.time() - t0, 1)})
+        log(f"[surrogate] epoch {epoch} loss {acc:.4e} ({time.time() - t0:.0f}s)")
+    return st.params, hist
+
+
+def predict(model, params, x, batch=4):
+    import torch
+    out = torch.empty((x.shape[0], 1) + x.shape[2:], dtype=torch.float32, device=x.device)
+    for s in range(0, x.shape[0], batch):
+        model.forward(params, x[s:s + batch], out[s:s + batch])
+    return out
+
+
+def evaluate(model, params, ds: Dataset, train_ratio: float) -> dict:
+    """Focal errors of the surrogate and of the no-learning baseline on ds."""
+    yhat = predict(model, params, ds.x).cpu().numpy()[:, 0]
+    errs, dists, base = [], [], []
+    for q in range(ds.x.shape[0]):
+        mask = ds.masks[q]
+        Ph = ds.pref[q] * np.exp(yhat[q])
+        Pm = np.where(mask, Ph, -1.0)
+        errs.append(abs(Pm.max() - ds.peak_post[q]) / ds.peak_post[q])
+        a = np.array(np.unravel_index(Pm.argmax(), Pm.shape))
+        dists.append(float(np.linalg.norm(a - ds.argmax_post[q])))
+        base.append(abs(train_ratio * ds.free_post[q] - ds.peak_post[q]) / ds.peak_post[q])
+    errs, dists, base = map(np.array, (errs, dists, base))
+    pct = lambda a, p: float(np.percentile(a, p))
+    return {"n": int(len(errs)), "focal_err_mean": float(errs.mean()),
+            "focal_err_median": pct(errs, 50), "focal_err_p90": pct(errs, 90),
+            "focal_err_max": float(errs.max()), "frac_within_5pct": float((errs <= 0.05).mean()),
+            "focal_dist_mean_vox": float(dists.mean()),
+            "frac_focal_dist_le_2": float((dists <= 2.0).mean()),
+            "baseline_focal_err_mean": float(base.mean()),
+            "baseline_focal_err_median": pct(base, 50)}
+
+
+class Gate:
+    """In-distribution test for the surrogate; anything outside the ranges
+    seen in training goes to the FDTD solve."""
+
+    def __init__(self, stats):
+        self.freqs = sorted({s["freq_hz"] for s in stats})
+        self.lo = {k: min(s[k] for s in stats) for k in ("bone_frac", "trab_frac")}
+        self.hi = {k: max(s[k] for s in stats) for k in ("bone_frac", "trab_frac")}
+        self.max_index = max(s["max_index"] for s in stats)
+
+    def accepts(self, st) -> bool:
+        if st["freq_hz"] not in self.freqs or st["max_index"] > self.max_index:
+            return False
+        return all(self.lo[k] <= st[k] <= self.hi[k] for k in self.lo)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--eval", type=int, default=200)
+    ap.add_argument("--seconds", type=float, default=420.0)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--width", type=int, default=32)
+    ap.add_argument("--layers", type=int, default=4)
+    ap.add_argument("--modes", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    synth = _synth()
+    tr_seeds = list(range(10000, 10000 + args.train))
+    ev_seeds = list(range(20000, 20000 + args.eval))
+    t0 = time.time()
+    dtr = generate(tr_seeds, args.n)
+    t_gen = time.time() - t0
+    dev = generate(ev_seeds, args.n, keep_masks=True)
+    ratio = float(np.mean(dtr.peak_post / dtr.free_post))
+    model = sg.Surrogate(n=args.n, cin=4, width=args.width, layers=args.layers,
+                         mx=args.modes, my=args.modes, mz=args.modes)
+    params, hist = train(model, dtr, args.seconds, batch=args.batch, lr=args.lr)
+    res = evaluate(model, params, dev, ratio)
+    gate = Gate(dtr.stats)
+    in_dist = float(np.mean([gate.accepts(s) for s in dev.stats]))
+    odd = synth.surrogate_case(30000, args.n)
+    odd.freq_hz = 1e6
+    odd_stats = ood_stats(odd)
+    # throughput: surrogate (free field + features + network) vs plain FDTD, one at a time
+    cases = [synth.surrogate_case(s, args.n) for s in ev_seeds[:16]]
+    plans = [bb.Plan.from_case(c) for c in cases]
+    wss = [p.workspace() for p in plans]
+    mats = [torch.from_numpy(c.mat).cuda() for c in cases]
+    src = torch.empty((args.n, args.n), dtype=torch.complex64, device="cuda")
+    peak = torch.empty((args.n,) * 3, dtype=torch.float32, device="cuda")
+    for p, w, m, c in zip(plans, wss, mats, cases):       # capture + warm
+        p.source_rayleigh(c.transducer, src, w)
+        p.solve(m, src, peak, w)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p, w, m, c in zip(plans, wss, mats, cases):
+        p.source_rayleigh(c.transducer, src, w)
+        p.solve(m, src, peak, w)
+    torch.cuda.synchronize()
+    fdtd_sps = len(cases) / (time.perf_counter() - t1)
+    free = torch.empty((args.n,) * 3, dtype=torch.complex64, device="cuda")
+    x1 = torch.empty((1, 4) + (args.n,) * 3, dtype=torch.float32, device="cuda")
+    y1 = torch.empty((1, 1) + (args.n,) * 3, dtype=torch.float32, device="cuda")
+    tables = []
+    for c in cases:
+        tb = np.zeros((c.materials.shape[0], 2), dtype=np.float32)
+        tb[:, 0] = c.materials[:, 1] / synth.C_WATER - 1.0
+        tb[:, 1] = c.materials[:, 0] / synth.RHO_WATER - 1.0
+        tables.append(torch.from_numpy(tb).cuda())
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for p, w, m, c, tb in zip(plans, wss, mats, cases, tables):
+            p.rayleigh_volume(c.transducer, free, w)
+            sg.features(m, tb, free, x1[0])
+            model.forward(params, x1, y1)
+        torch.cuda.synchronize()
+        sur_sps = len(cases) / (time.perf_counter() - t1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    yb = predict(model, params, dev.x, batch=args.batch)
+    torch.cuda.synchronize()
+    sur_batched_sps = dev.x.shape[0] / (time.perf_counter() - t1)
+    del yb
+    out = {"config": {"n": args.n, "width": args.width, "layers": args.layers,
+                      "modes": args.modes, "params": model.n_params, "train": args.train,
+                      "eval": args.eval, "batch": args.batch, "seconds": args.seconds},
+           "generation_s": round(t_gen, 1), "training": hist, "eval": res,
+           "train_mean_ratio": ratio, "gate_in_distribution_frac": in_dist,
+           "gate_rejects_1MHz": not gate.accepts(odd_stats),
+           "fdtd_solves_per_s": round(fdtd_sps, 2),
+           "surrogate_solves_per_s": round(sur_sps, 2),
+           "surrogate_batched_solves_per_s": round(sur_batched_sps, 2)}
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: out[k] for k in ("eval", "fdtd_solves_per_s", "surrogate_solves_per_s",
+                                          "surrogate_batched_solves_per_s")}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -203,8 +203,9 @@ def bowl_focus_for_standoff(zs: float, radius: float, focal: float, axis, stando
 
 def skull_map(nx: int, ny: int, nz: int, dx: float, zs: float, seed: int,
               r_out: float = 70e-3, centre_depth: float = 80e-3,
-              axis_ij=None, chunk: int = 16) -> np.ndarray:
-    """uint8 [nz, ny, nx] skull-shell map (indices as ``skull_materials``)."""
+              axis_ij=None, chunk: int = 16, thick_scale: float = 1.0) -> np.ndarray:
+    """uint8 [nz, ny, nx] skull-shell map (indices as ``skull_materials``);
+    thickness 6.5 +- 1.5 mm times ``thick_scale``."""
     rng = np.random.default_rng(seed)
     ci, cj = (nx // 2, ny // 2) if axis_ij is None else axis_ij
     centre = np.array([ci * dx, cj * dx, zs + centre_depth])
@@ -212,7 +213,7 @@ def skull_map(nx: int, ny: int, nz: int, dx: float, zs: float, seed: int,
     hi = (nx * dx, ny * dx, nz * dx)
     n_thick = _ValueNoise(rng, 10e-3, lo, hi)
     n_poro = _ValueNoise(rng, 4e-3, lo, hi)
-    t_max = 8.0e-3
+    t_max = 8.0e-3 * thick_scale
     out = np.zeros((nz, ny, nx), dtype=np.uint8)
     xs = np.arange(nx) * dx
     ys = np.arange(ny) * dx
@@ -229,7 +230,7 @@ def skull_map(nx: int, ny: int, nz: int, dx: float, zs: float, seed: int,
         sx = centre[0] + rx[cand] * s
         sy = centre[1] + ry[cand] * s
         sz = centre[2] + rz[cand] * s
-        thick = 6.5e-3 + 1.5e-3 * n_thick(sx, sy, sz)
+        thick = (6.5e-3 + 1.5e-3 * n_thick(sx, sy, sz)) * thick_scale
         depth = r_out - rc
         bone = depth <= thick
         cort = bone & ((depth < 0.1 * thick) | (depth > 0.9 * thick))
@@ -248,8 +249,11 @@ def skull_map(nx: int, ny: int, nz: int, dx: float, zs: float, seed: int,
 def skull_case(nx: int = 200, ny: int = 200, nz: int = 280, freq_hz: float = 500e3,
                ppw: float = 6.0, n_steps: int = 3000, seed: int = 1, pml: int = 8,
                aperture: float = 64e-3, fnum: float = 1.0, tilt=(0.0, 0.0),
-               standoff: float = 3e-3, name: str = "skull", build_map: bool = True) -> Case:
-    """Skull-shell workload with a focused bowl (aperture = diameter)."""
+               standoff: float = 3e-3, name: str = "skull", build_map: bool = True,
+               surface_depth: float = 10e-3, thick_scale: float = 1.0) -> Case:
+    """Skull-shell workload with a focused bowl (aperture = diameter); the
+    shell's outer surface crosses the axis ``surface_depth`` after the source
+    plane."""
     c = Case(name, nx, ny, nz, pml, freq_hz, ppw, n_steps, skull_materials(freq_hz), None, None)
     dx, zs = c.dx, c.source_plane_z()
     radius = 0.5 * aperture
@@ -260,7 +264,8 @@ def skull_case(nx: int = 200, ny: int = 200, nz: int = 280, freq_hz: float = 500
     apex, ax = bowl_pose((ci * dx, cj * dx, fz), tilt[0], tilt[1], focal)
     c.transducer = Transducer(1, radius, focal, apex, ax)
     if build_map:
-        c.mat = skull_map(nx, ny, nz, dx, zs, seed)
+        c.mat = skull_map(nx, ny, nz, dx, zs, seed, centre_depth=surface_depth + 70e-3,
+                          thick_scale=thick_scale)
     return c
 
 
@@ -301,6 +306,28 @@ def batch_cases(n: int = 32, lo: int = 96, hi: int = 160, build_map: bool = True
                        name=f"batch{s}", build_map=build_map)
         cases.append(c)
     return cases
+
+
+def surrogate_case(seed: int, n: int = 64, build_map: bool = True) -> Case:
+    """n^3 sample for the learned surrogate, batch-sweep style: frequency
+    BATCH_FREQS[seed % 3], PPW 6, bowl tilts from PCG64(seed) in +-15 degrees,
+    bowl aperture 0.6 x lateral extent, F#1, rim 3 mm before the source plane.
+    The shell's outer surface crosses the axis 15 % of the interior depth after
+    the source plane and its thickness is scaled to at most a quarter of that
+    depth, so the focus lies beyond the skull at every frequency."""
+    rng = np.random.default_rng(seed)
+    tx, ty = (float(v) for v in rng.uniform(-15.0, 15.0, size=2))
+    f = BATCH_FREQS[seed % 3]
+    ppw = 6.0
+    dx = C_WATER / (f * ppw)
+    pml = 8
+    depth = (n - 2 * pml) * dx
+    periods = math.ceil(1.5 * n / ppw) + 2
+    return skull_case(n, n, n, f, ppw, periods * 23, seed=seed, pml=pml,
+                      aperture=0.6 * n * dx, fnum=1.0,
+                      tilt=(math.radians(tx), math.radians(ty)), name=f"sur{seed}",
+                      build_map=build_map, surface_depth=0.15 * depth,
+                      thick_scale=min(1.0, 0.25 * depth / 6.5e-3))
 
 
 def random_small_case(seed: int, n=(24, 40), n_mat: int = 4, pml: int = 4,

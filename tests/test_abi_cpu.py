@@ -20,7 +20,7 @@ def declared_functions():
     for h in os.listdir(os.path.join(ROOT, "include")):
         if h.endswith(".h"):
             txt = open(os.path.join(ROOT, "include", h)).read()
-            names += re.findall(r"^\s*(?:int|void|const char \*)\s*(\w+)\s*\(", txt, re.M)
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\**\s*(bb(?:fd|sur)_\w+)\s*\(", txt, re.M)
     return sorted(set(names))
 
 
@@ -28,6 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = C.CDLL(bb.bbfd.LIB_PATH)
     names = declared_functions()
     assert "bbfd_solve" in names and "bbfd_source_rayleigh" in names
+    assert "bbsur_train_step" in names and "bbfd_batch_solve" in names
     for n in names:
         assert hasattr(lib, n), n
     assert set(bb.EXPORTS) <= set(names)

@@ -1,0 +1,88 @@
+"""Batched sweeps (uneven sizes, frequencies and step counts in one captured
+persistent launch) against the same problems solved one by one."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2301_12727_amd as bb
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def uneven_cases():
+    freqs = (250e3, 500e3, 700e3, 500e3, 250e3)
+    cases = []
+    for s, f in enumerate(freqs):
+        c = synth.random_small_case(40 + s, n=(24, 44), n_steps=30 + 17 * s, freq_hz=f)
+        cases.append(c)
+    return cases
+
+
+def batch_inputs(b, cases, ws):
+    mats = [torch.from_numpy(c.mat).cuda() for c in cases]
+    srcs = [torch.empty((c.ny, c.nx), dtype=torch.complex64, device="cuda") for c in cases]
+    for i, c in enumerate(cases):
+        b.source_rayleigh(i, c.transducer, srcs[i], ws)
+    peaks = [torch.empty((c.nz, c.ny, c.nx), dtype=torch.float32, device="cuda") for c in cases]
+    return mats, srcs, peaks
+
+
+def test_batched_equals_single_solves(tmp_path):
+    cases = uneven_cases()
+    say("[batch] sizes " + ", ".join(f"{c.nx}x{c.ny}x{c.nz}/{c.n_steps}" for c in cases))
+    single = []
+    for c in cases:
+        P, idx, val, _ = bb.run_case(c)
+        single.append((P.cpu().numpy(), idx, val))
+    b = bb.Batch(cases)
+    ws = b.workspace()
+    mats, srcs, peaks = batch_inputs(b, cases, ws)
+    for shape in ((4, 1024, 16), (1, 64, 4), (8, 3, 7), (2, 5000, 64)):
+        say(f"[batch] shape {shape}")
+        b.set_shape(*shape)
+        b.solve(mats, srcs, peaks, ws)
+        for _ in range(2):                   # replay of the captured graph
+            b.solve(mats, srcs, peaks, ws)
+        for i, c in enumerate(cases):
+            idx, val = b.status(ws, i)
+            got = peaks[i].cpu().numpy()
+            assert np.array_equal(got, single[i][0]), (shape, i)
+            assert idx == single[i][1] and val == single[i][2]
+    cache = str(tmp_path / "tune.txt")
+    best, shape = b.autotune(mats, srcs, peaks, ws, cache_path=cache, probe_steps=3)
+    say(f"[batch] autotuned shape {shape}, {best:.3f} ms per 3 steps")
+    assert best > 0 and os.path.exists(cache)
+    b.solve(mats, srcs, peaks, ws)
+    for i in range(len(cases)):
+        b.status(ws, i)
+        assert np.array_equal(peaks[i].cpu().numpy(), single[i][0])
+    # a second batch of the same size class reads the cached shape
+    b2 = bb.Batch(cases)
+    ws2 = b2.workspace()
+    m2, s2, p2 = batch_inputs(b2, cases, ws2)
+    best2, shape2 = b2.autotune(m2, s2, p2, ws2, cache_path=cache, probe_steps=3)
+    assert shape2[:3] == shape[:3] and best2 == pytest.approx(best)
+
+
+def test_batch_reports_per_solve_errors():
+    cases = uneven_cases()[:3]
+    cases[1].mat = cases[1].mat.copy()
+    cases[1].mat[2, 3, 4] = cases[1].materials.shape[0]     # out-of-range index in solve 1 only
+    b = bb.Batch(cases)
+    ws = b.workspace()
+    mats, srcs, peaks = batch_inputs(b, cases, ws)
+    b.solve(mats, srcs, peaks, ws)
+    b.status(ws, 0)
+    b.status(ws, 2)
+    with pytest.raises(bb.BBFDError) as e:
+        b.status(ws, 1)
+    assert e.value.code == bb.EINDEX

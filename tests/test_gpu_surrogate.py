@@ -1,0 +1,112 @@
+"""Surrogate kernels on the GPU: the BF16 matrix-core GEMM (exact against
+numpy on BF16-rounded operands) and the network's forward pass and gradients
+against the FP64 numpy reference (FFT-based)."""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import nn_ref
+import paper_2301_12727_amd as bb
+from paper_2301_12727_amd import surrogate as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def bf16(a):
+    """Round FP32 to BF16 (nearest even), returned as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N,K,batch,trans", [(64, 64, 32, 1, "nn"), (50, 70, 45, 3, "nn"),
+                                                (33, 17, 130, 2, "tn"), (1, 300, 7, 2, "nt"),
+                                                (128, 96, 64, 1, "tt")])
+def test_gemm_matches_bf16_reference(M, N, K, batch, trans):
+    rng = np.random.default_rng(M * 1000 + N)
+    A = rng.normal(size=(batch, M, K)).astype(np.float32)
+    B = rng.normal(size=(batch, K, N)).astype(np.float32)
+    C0 = rng.normal(size=(batch, M, N)).astype(np.float32)
+    bias = rng.normal(size=M).astype(np.float32)
+    # storage layouts: "t" stores the operand transposed in memory
+    Ad = np.ascontiguousarray(A.transpose(0, 2, 1) if trans[0] == "t" else A)
+    Bd = np.ascontiguousarray(B.transpose(0, 2, 1) if trans[1] == "t" else B)
+    a_str = (M * K, 1, M) if trans[0] == "t" else (M * K, K, 1)
+    b_str = (K * N, 1, K) if trans[1] == "t" else (K * N, N, 1)
+    tA, tB = torch.from_numpy(Ad).cuda(), torch.from_numpy(Bd).cuda()
+    tC = torch.from_numpy(C0.copy()).cuda()
+    tb = torch.from_numpy(bias).cuda()
+    sg.gemm(tA, a_str, tB, b_str, tC, (M * N, N, 1), M, N, K, batch, alpha=1.5, beta=0.5, bias=tb)
+    torch.cuda.synchronize()
+    want = 1.5 * np.einsum("bmk,bkn->bmn", bf16(A), bf16(B)) + 0.5 * C0 + bias[None, :, None]
+    got = tC.cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say(f"[gemm] {M}x{N}x{K} b{batch} {trans}: max rel {err:.2e}")
+    assert err < 1e-5
+
+
+CFG = nn_ref.Config(n=16, cin=4, width=8, layers=2, mx=3, my=3, mz=3)
+
+
+def _setup(batch, seed):
+    rng = np.random.default_rng(seed)
+    p = nn_ref.init_params(CFG, seed).astype(np.float32)
+    p += rng.normal(0, 0.02, p.shape).astype(np.float32)
+    x = rng.normal(0, 1, (batch, CFG.cin) + (CFG.n,) * 3).astype(np.float32)
+    return p, x
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def test_forward_matches_fp64_reference():
+    p, x = _setup(2, 1)
+    model = sg.Surrogate(**CFG.__dict__)
+    assert model.n_params == p.size
+    y = model.forward(torch.from_numpy(p).cuda(), torch.from_numpy(x).cuda())
+    ref = nn_ref.forward(p.astype(np.float64), x.astype(np.float64), CFG)
+    err = rel(y.cpu().numpy(), ref)
+    say(f"[surrogate] forward rel-L2 {err:.3e}")
+    assert err < 2e-2
+
+
+def test_gradients_match_fp64_reference():
+    p, x = _setup(2, 2)
+    rng = np.random.default_rng(3)
+    dy = rng.normal(0, 1, (2, 1) + (CFG.n,) * 3).astype(np.float32)
+    model = sg.Surrogate(**CFG.__dict__)
+    g = model.backward(torch.from_numpy(p).cuda(), torch.from_numpy(x).cuda(),
+                       torch.from_numpy(dy).cuda()).cpu().numpy()
+    gref, _, _ = nn_ref.backward(p.astype(np.float64), x.astype(np.float64),
+                                 dy.astype(np.float64), CFG)
+    errs = {}
+    off = 0
+    for name, shape in nn_ref.param_layout(CFG):
+        n = int(np.prod(shape))
+        errs[name] = rel(g[off:off + n], gref[off:off + n])
+        off += n
+    say("[surrogate] grad rel-L2 " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert rel(g, gref) < 2e-2
+    assert max(errs.values()) < 5e-2
+
+
+def test_training_reduces_loss_on_a_fixed_batch():
+    p, x = _setup(2, 4)
+    rng = np.random.default_rng(5)
+    target = np.tanh(nn_ref.forward(nn_ref.init_params(CFG, 9), x.astype(np.float64), CFG))
+    model = sg.Surrogate(**CFG.__dict__)
+    st = model.train_state(torch.from_numpy(p).cuda())
+    xs, ts = torch.from_numpy(x).cuda(), torch.from_numpy(target.astype(np.float32)).cuda()
+    losses = [model.train_step(st, xs, ts, lr=3e-3) for _ in range(60)]
+    say(f"[surrogate] loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert losses[-1] < 0.5 * losses[0]
+    del rng
