@@ -47,36 +47,42 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def slab_cells(case) -> list:
-    """Cells inside the absorbing layer of each axis (x, y, z slabs)."""
-    L = case.pml
-    n = (case.nx, case.ny, case.nz)
-    out = []
-    for a in range(3):
-        others = 1
-        for b in range(3):
-            if b != a:
-                others *= n[b]
-        out.append(2 * L * others)
-    return out
-
-
-def algorithmic_bytes(case, info) -> dict:
+def algorithmic_bytes(case, info, classes) -> dict:
     """Bytes each kernel must move per launch at perfect on-chip reuse (FP32
-    state, 1-byte index), averaged over the time loop.
-      velocity: read 6 stresses + 3 velocities + index, write 3 velocities
-                = 49 B/cell, + 3 layer memories read+write (24 B) per slab cell,
-                + the source plane (8 B per column)
-      stress:   read 3 velocities + 6 stresses + 6 memories + index, write 6 +
-                6 = 109 B/cell, + 3 layer memories (24 B) per slab cell,
-                + 8 B/cell (peak read+write) in capture steps."""
+    state, 1-byte index), averaged over the time loop.  ``classes`` is the
+    library's row-segment class map: cells of class > 0 take the acoustic branch.
+      velocity, elastic cell: read 6 stresses + 3 velocities + index, write 3
+                velocities = 49 B; acoustic cell: read 1 normal stress + 3
+                velocities, write 3 velocities = 28 B.  Per absorbing-layer axis
+                the cell lies in: 3 (elastic) or 1 (acoustic) layer memories read
+                and written (8 B each).  Source plane: 8 B per column.
+      stress,   elastic cell: read 3 velocities + 6 stresses + 6 memories +
+                index, write 6 + 6 = 109 B; acoustic cell: read 3 velocities +
+                1 normal stress, write 3 normal stresses = 28 B.  Layer memories
+                as above.  Capture steps add 8 B/cell (peak read + write).
+      Both read one class byte per 64-cell row segment."""
+    import numpy as np
+    nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
+    seg = (classes != 0)
+    fluid = np.repeat(seg, 64, axis=2)[:, :, :nx]
     cells = case.cells
-    slabs = sum(slab_cells(case))
+    nf = int(fluid.sum())
+    ne = cells - nf
+
+    # (cell, slab axis) pairs in the absorbing layer, all and acoustic only
+    slab_tot = 2 * L * (ny * nz + nx * nz + nx * ny)
+    slab_fl = (int(fluid[:, :, :L].sum()) + int(fluid[:, :, nx - L:].sum())
+               + int(fluid[:, :L, :].sum()) + int(fluid[:, ny - L:, :].sum())
+               + int(fluid[:L].sum()) + int(fluid[nz - L:].sum()))
+    slab_el = slab_tot - slab_fl
     steps = case.n_steps
     cap_steps = steps - info["capture_start"]
-    vel = 49 * cells + 24 * slabs + 8 * case.nx * case.ny
-    stress = 109 * cells + 24 * slabs + 8 * cells * cap_steps / steps
-    return {"velocity": vel, "stress": stress, "per_cell_update": (vel + stress) / cells}
+    cls_bytes = classes.size
+    vel = 49 * ne + 28 * nf + 24 * slab_el + 8 * slab_fl + 8 * nx * ny + cls_bytes
+    stress = (109 * ne + 28 * nf + 24 * slab_el + 8 * slab_fl + cls_bytes
+              + 8 * cells * cap_steps / steps)
+    return {"velocity": vel, "stress": stress, "per_cell_update": (vel + stress) / cells,
+            "acoustic_fraction": nf / cells}
 
 
 def load_traffic(kernel: str, workload: str):
@@ -238,7 +244,7 @@ def main():
     ms_v, ms_s = plan.solve_profiled(mat, src, peak, ws)
     pidx2, _ = plan.status(ws)
     assert pidx2 == pidx
-    ab = algorithmic_bytes(case, info)
+    ab = algorithmic_bytes(case, info, plan.segment_classes(ws))
     avg = {"velocity": ms_v / case.n_steps, "stress": ms_s / case.n_steps}
     dom = "stress" if avg["stress"] >= avg["velocity"] else "velocity"
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
@@ -248,7 +254,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"k_{dom}", "avg_launch_ms": round(avg[dom], 5),
             "algorithmic_bytes_per_launch": int(ab[dom]),
-            "bytes_per_cell_update": round(ab["per_cell_update"], 2)}
+            "algorithmic_bytes_velocity": int(ab["velocity"]),
+            "algorithmic_bytes_stress": int(ab["stress"]),
+            "bytes_per_cell_update": round(ab["per_cell_update"], 2),
+            "acoustic_cell_fraction": round(ab["acoustic_fraction"], 4)}
 
     out = {
         "metric": "Gcell-updates/s",

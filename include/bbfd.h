@@ -156,6 +156,18 @@ int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *
 int bbfd_status(const bbfd_plan *plan, const void *workspace, int64_t *peak_index,
                 float *peak_value, void *stream);
 
+/* Diagnostic: the row-segment classes the last solve in this workspace used.
+   Row segment s of row (j, k) covers cells x in [64 s, min(64 s + 64, nx)); its
+   class is m + 1 when every cell within two cells of the segment (x, y and z,
+   edge cells standing in for cells beyond the grid) holds the same lossless
+   fluid material m (zero shear speed and zero attenuation), else 0.  Class m + 1
+   segments take the acoustic branch of the step kernels (one normal stress read,
+   no memory variables); the result is the same either way.  classes (host)
+   receives nseg * ny * nz bytes, nseg = ceil(nx / 64), ordered [nz][ny][nseg];
+   n is its size (BBFD_EINVAL if smaller).  Synchronises stream. */
+int bbfd_segment_classes(const bbfd_plan *plan, const void *workspace, uint8_t *classes,
+                         uint64_t n, void *stream);
+
 /* ---- Batched sweeps: many independent solves of uneven size in one launch.
    Each problem keeps its own grid, frequency, time step, tables and step count;
    a persistent pair of kernels per time step walks a ragged (solve, tile)

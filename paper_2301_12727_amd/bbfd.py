@@ -53,6 +53,7 @@ class PlanInfo(C.Structure):
 EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_material_constants", "bbfd_transducer_elements", "bbfd_source_rayleigh",
            "bbfd_solve", "bbfd_solve_direct", "bbfd_solve_profiled", "bbfd_status",
+           "bbfd_segment_classes",
            "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
            "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
            "bbfd_batch_status", "bbfd_batch_autotune"]
@@ -81,6 +82,7 @@ def lib():
         L.bbfd_solve_direct.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
         L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
         L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
+        L.bbfd_segment_classes.argtypes = [vp, vp, vp, C.c_uint64, vp]
         L.bbfd_last_error.restype = C.c_char_p
         L.bbfd_batch_create.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(vp)]
         L.bbfd_batch_destroy.argtypes = [vp]
@@ -218,6 +220,16 @@ class Plan:
         _check(lib().bbfd_status(self.h, C.c_void_p(ws.data_ptr()), C.byref(idx), C.byref(val),
                                  C.c_void_p(_stream(stream))))
         return int(idx.value), float(val.value)
+
+    def segment_classes(self, ws, stream=None):
+        """Row-segment classes of the last solve in ws, uint8 [nz][ny][ceil(nx/64)]
+        (0: elastic branch, m + 1: acoustic branch for lossless fluid m)."""
+        nz, ny, nx = self.shape
+        out = np.zeros((nz, ny, (nx + 63) // 64), dtype=np.uint8)
+        _check(lib().bbfd_segment_classes(self.h, C.c_void_p(ws.data_ptr()),
+                                          out.ctypes.data_as(C.c_void_p), out.size,
+                                          C.c_void_p(_stream(stream))))
+        return out
 
 
 def _ptr_array(tensors):

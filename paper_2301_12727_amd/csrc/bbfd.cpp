@@ -27,7 +27,7 @@ hipError_t launch_stress(const StepArgs &a, hipStream_t s);
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
                        hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
-hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, const Grid &g, int nseg,
+hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, const Grid &g, int nseg, int kpad,
                            const float *lut, hipStream_t s);
 hipError_t launch_argmax(const float *P, int nx, int ny, int nz, int L, float *pv, long long *pi,
                          Status *st, hipStream_t s);
@@ -36,7 +36,7 @@ hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, int plan
                            double z0, double kw, double pre, float2 *out, hipStream_t s);
 hipError_t launch_batched_step(int by, const StepArgs *desc, const BatchTile *tiles, int n_tiles,
                                const float2 *coef, const int *cap, int max_steps, int n,
-                               int blocks, hipStream_t s);
+                               int blocks, int max_mat, hipStream_t s);
 }  // namespace bbfd
 
 using namespace bbfd;
@@ -101,6 +101,7 @@ struct bbfd_plan {
   std::vector<float> src_c, src_s;
   int kchunk = 1;
   int nseg = 1;
+  int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
          off_cls = 0, off_state = 0, off_psi = 0, ws_bytes = 0;
   std::mutex mu;
@@ -251,8 +252,12 @@ void layout(bbfd_plan *pl) {
   g.rows = p.ny + 2 * kGhost;
   g.plane = (long long)g.pitch * g.rows;
   g.stride = (long long)round_up(kX0 + (size_t)g.plane * (p.nz + 2 * kGhost), 64);
-  const long long nbxy = (long long)((p.nx + 63) / 64) * ((p.ny + 3) / 4);
-  long long kc = (nbxy * p.nz + 4095) / 4096;
+  const long long nbxy = (long long)((p.nx + kSeg - 1) / kSeg) * ((p.ny + kRows - 1) / kRows);
+  // z cells per tile: at least ~8192 tiles (a few rounds of blocks over the
+  // 256 CUs) and at most 8 planes, the shortest march that measured fastest
+  // on the 400x400x520 workload (longer marches gain no reuse: every plane's
+  // loads are issued afresh)
+  const long long kc = std::min(8LL, (nbxy * p.nz) / 8192);
   pl->kchunk = (int)std::max(1LL, std::min<long long>(kc, p.nz));
   size_t o = 0;
   pl->off_status = o; o += 256;
@@ -262,7 +267,8 @@ void layout(bbfd_plan *pl) {
   pl->off_pi = o; o += round_up(argmax_partials() * sizeof(long long), 256);
   pl->off_idx = o; o += round_up((size_t)g.stride, 256);
   pl->nseg = (p.nx + kSeg - 1) / kSeg;
-  pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * p.nz, 256);
+  pl->kpad = (int)round_up((size_t)p.nz, 4) + 4;
+  pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
   pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
   pl->ws_bytes = o;
@@ -283,7 +289,9 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.idx = (const uint8_t *)(ws + pl->off_idx);
   a.cls = (const uint8_t *)(ws + pl->off_cls);
   a.nseg = pl->nseg;
+  a.kpad = pl->kpad;
   a.lut = (const float *)(ws + pl->off_lut);
+  a.n_mat = pl->prob.n_materials;
   const float4 *t = (const float4 *)(ws + pl->off_pml);
   a.pml.x = t;
   a.pml.y = t + pl->prob.nx;
@@ -297,6 +305,8 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.relax_a = pl->relax_a;
   a.relax_b = pl->relax_b;
   a.kchunk = pl->kchunk;
+  a.nby = (pl->prob.ny + kRows - 1) / kRows;
+  a.n_tiles = pl->nseg * a.nby * ((pl->prob.nz + pl->kchunk - 1) / pl->kchunk);
   return a;
 }
 
@@ -346,7 +356,7 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
       hipSuccess)
     return hip_fail(e, "index pack");
   if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_cls), pl->g,
-                           pl->nseg, (const float *)(ws + pl->off_lut), s)) != hipSuccess)
+                           pl->nseg, pl->kpad, (const float *)(ws + pl->off_lut), s)) != hipSuccess)
     return hip_fail(e, "segment classes");
   return BBFD_OK;
 }
@@ -675,6 +685,23 @@ int bbfd_status(const bbfd_plan *pl, const void *workspace, int64_t *peak_index,
   return BBFD_OK;
 }
 
+int bbfd_segment_classes(const bbfd_plan *pl, const void *workspace, uint8_t *classes,
+                         uint64_t n, void *stream) {
+  if (!pl || !workspace || !classes) return fail(BBFD_EINVAL, "null argument");
+  const int nx = pl->nseg, ny = pl->g.ny, nz = pl->g.nz, kp = pl->kpad;
+  if (n < (uint64_t)nx * ny * nz) return fail(BBFD_EINVAL, "classes buffer holds fewer than nseg*ny*nz bytes");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream sync");
+  std::vector<uint8_t> col((size_t)nx * ny * kp);  // device layout: [ny][nseg][kpad]
+  e = hipMemcpy(col.data(), (const char *)workspace + pl->off_cls, col.size(), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "class read");
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int sg = 0; sg < nx; ++sg)
+        classes[((size_t)k * ny + j) * nx + sg] = col[((size_t)j * nx + sg) * kp + k];
+  return BBFD_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches
@@ -688,6 +715,7 @@ struct bbfd_batch {
   size_t max_tiles = 0;         // capacity of the tile table region
   // launch shape (autotuned): rows per block, persistent blocks, z cells per tile
   int by = 4, blocks = 1024, kchunk = 16;
+  int max_mat = 1;              // largest material table (LDS staging size)
   std::vector<BatchTile> tiles;
   std::vector<int> live;        // live tiles at each step (a prefix of tiles)
   StepArgs *h_desc = nullptr;   // pinned staging, made at the first solve
@@ -812,7 +840,7 @@ int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *
     if ((e = launch_batched_step(b->by, (const StepArgs *)(ws + b->off_desc),
                                  (const BatchTile *)(ws + b->off_tiles), b->live[k],
                                  (const float2 *)(ws + b->off_coef), (const int *)(ws + b->off_cap),
-                                 b->max_steps, k, b->blocks, s)) != hipSuccess)
+                                 b->max_steps, k, b->blocks, b->max_mat, s)) != hipSuccess)
       return hip_fail(e, "batched step launch");
   if (steps >= 0) return BBFD_OK;
   for (size_t q = 0; q < n; ++q) {
@@ -858,6 +886,7 @@ int bbfd_batch_create(const bbfd_problem *probs, int32_t n, bbfd_batch **out) {
     }
     b->plans.push_back(pl);
     b->max_steps = std::max(b->max_steps, pl->prob.n_steps);
+    b->max_mat = std::max(b->max_mat, pl->prob.n_materials);
   }
   b->order.resize(n);
   for (int s = 0; s < n; ++s) b->order[s] = s;
@@ -1039,7 +1068,7 @@ int bbfd_batch_autotune(bbfd_batch *b, const uint8_t *const *mat, const float *c
                                              (const BatchTile *)((char *)workspace + b->off_tiles),
                                              b->live[k], (const float2 *)((char *)workspace + b->off_coef),
                                              (const int *)((char *)workspace + b->off_cap), b->max_steps, k,
-                                             b->blocks, s);
+                                             b->blocks, b->max_mat, s);
           if (e != hipSuccess) {
             rc = hip_fail(e, "tuning launch");
             goto done;

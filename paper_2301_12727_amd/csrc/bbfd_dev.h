@@ -28,18 +28,21 @@ struct Grid {
   }
 };
 
-// Per-material FP32 table (host-derived in FP64, scaled by dt/dx):
+// Per-material FP32 table (host-derived in FP64, scaled by dt/dx).  The four
+// moduli of a cell centre and the two edge-average inputs are adjacent so the
+// kernels fetch them as one float4 and one float2.
 enum LutField {
-  kRhoS = 0,   // rho * dx / dt           (buoyancy of a face: 2 / (rhoS_a + rhoS_b))
-  kPiU = 1,    // pi_U * dt / dx          (unrelaxed P modulus)
-  kMuU = 2,    // mu_U * dt / dx          (unrelaxed shear modulus)
-  kPiTau = 3,  // pi_R * tau_P * dt / dx  (memory-variable target, normal part)
-  kMuTau = 4,  // mu_R * tau_S * dt / dx  (memory-variable target, shear part)
+  kPiU = 0,    // pi_U * dt / dx          (unrelaxed P modulus)
+  kMuU = 1,    // mu_U * dt / dx          (unrelaxed shear modulus)
+  kPiTau = 2,  // pi_R * tau_P * dt / dx  (memory-variable target, normal part)
+  kMuTau = 3,  // mu_R * tau_S * dt / dx  (memory-variable target, shear part)
+  kInvMu = 4,  // dx / (mu_R * dt), +inf for fluids (edge harmonic mean)
   kTauS = 5,   // tau_S                   (edge average)
-  kInvMu = 6,  // dx / (mu_R * dt), +inf for fluids (edge harmonic mean)
+  kRhoS = 6,   // rho * dx / dt           (buoyancy of a face: 2 / (rhoS_a + rhoS_b))
   kLossless = 7,  // 1 for a fluid without attenuation (no shear, no memory), else 0
   kLutW = 8
 };
+constexpr int kMaxMaterials = 256;
 
 // Row segments: the kernels' waves cover 64 consecutive x cells of one row.
 // A segment's class is m + 1 when every cell within two cells of it (the
@@ -68,9 +71,11 @@ struct PmlTab {
 struct StepArgs {
   Grid g;
   const uint8_t *idx;     // padded, replicated ghosts
-  const uint8_t *cls;     // [nz][ny][nseg] segment classes
+  const uint8_t *cls;     // segment classes, [ny][nseg][kpad]: one z column per segment
   int nseg;               // ceil(nx / kSeg)
+  int kpad;               // round_up(nz, 4) + 4 bytes per class column
   const float *lut;       // kLutW floats per material
+  int n_mat;              // materials in lut
   PmlTab pml;
   float *f[kNState];      // padded state arrays
   float *psi[kNPsi];      // padded CPML memories (touched in the layer only)
@@ -80,8 +85,13 @@ struct StepArgs {
   float relax_b;          // 2 h / (1 + h)
   float src_c, src_s;     // per step: v_z face force src_c * Re S - src_s * Im S (x b_z)
   int capture;            // 1: update the peak map after this step
-  int kchunk;             // z cells per block
+  int kchunk;             // z cells per tile
+  int nby;                // row blocks per plane (rows per block: kRows)
+  int n_tiles;            // x segments * row blocks * z chunks
 };
+
+// Rows of a single-solve tile (one wave per row).
+constexpr int kRows = 4;
 
 // Batched sweeps: one entry per (solve, tile); solves are ordered by
 // decreasing step count so the live tiles of step n are a prefix of the table.
