@@ -47,10 +47,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+KERNELS = ("velocity_ac", "velocity", "stress_ac", "stress")
+
+
 def algorithmic_bytes(case, info, classes) -> dict:
-    """Bytes each kernel must move per launch at perfect on-chip reuse (FP32
-    state, 1-byte index), averaged over the time loop.  ``classes`` is the
-    library's row-segment class map: cells of class > 0 take the acoustic branch.
+    """Bytes each step kernel must move per launch at perfect on-chip reuse
+    (FP32 state, 1-byte index), averaged over the time loop.  ``classes`` is
+    the library's row-segment class map: cells of class > 0 are acoustic (one
+    lossless fluid throughout the stencil's reach).  A tile (64 x tile_rows x
+    tile_planes cells) all of whose segments are acoustic runs the *_ac
+    kernels, every other tile the general ones.
       velocity, elastic cell: read 6 stresses + 3 velocities + index, write 3
                 velocities = 49 B; acoustic cell: read 1 normal stress + 3
                 velocities, write 3 velocities = 28 B.  Per absorbing-layer axis
@@ -59,30 +65,40 @@ def algorithmic_bytes(case, info, classes) -> dict:
       stress,   elastic cell: read 3 velocities + 6 stresses + 6 memories +
                 index, write 6 + 6 = 109 B; acoustic cell: read 3 velocities +
                 1 normal stress, write 3 normal stresses = 28 B.  Layer memories
-                as above.  Capture steps add 8 B/cell (peak read + write).
-      Both read one class byte per 64-cell row segment."""
+                as above.  Capture steps add 8 B/cell (peak read + write)."""
     import numpy as np
     nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
-    seg = (classes != 0)
+    R, K = int(info["tile_rows"]), int(info["tile_planes"])
+    seg = classes != 0                                     # [nz][ny][nseg]
+    nseg = seg.shape[2]
+    nby, nzc = -(-ny // R), -(-nz // K)
+    pad = np.ones((nzc * K, nby * R, nseg), dtype=bool)
+    pad[:nz, :ny] = seg
+    kind = pad.reshape(nzc, K, nby, R, nseg).all(axis=(1, 3))      # acoustic tiles
+    tile_ac = np.repeat(np.repeat(np.repeat(kind, K, 0)[:nz], R, 1)[:, :ny], 64, 2)[:, :, :nx]
     fluid = np.repeat(seg, 64, axis=2)[:, :, :nx]
-    cells = case.cells
-    nf = int(fluid.sum())
-    ne = cells - nf
-
-    # (cell, slab axis) pairs in the absorbing layer, all and acoustic only
-    slab_tot = 2 * L * (ny * nz + nx * nz + nx * ny)
-    slab_fl = (int(fluid[:, :, :L].sum()) + int(fluid[:, :, nx - L:].sum())
-               + int(fluid[:, :L, :].sum()) + int(fluid[:, ny - L:, :].sum())
-               + int(fluid[:L].sum()) + int(fluid[nz - L:].sum()))
-    slab_el = slab_tot - slab_fl
-    steps = case.n_steps
-    cap_steps = steps - info["capture_start"]
-    cls_bytes = classes.size
-    vel = 49 * ne + 28 * nf + 24 * slab_el + 8 * slab_fl + 8 * nx * ny + cls_bytes
-    stress = (109 * ne + 28 * nf + 24 * slab_el + 8 * slab_fl + cls_bytes
-              + 8 * cells * cap_steps / steps)
-    return {"velocity": vel, "stress": stress, "per_cell_update": (vel + stress) / cells,
-            "acoustic_fraction": nf / cells}
+    axes_in_layer = np.zeros((nz, ny, nx), dtype=np.int8)
+    for a, n in ((2, nx), (1, ny), (0, nz)):
+        sl = [slice(None)] * 3
+        sl[a] = np.r_[0:L, n - L:n]
+        axes_in_layer[tuple(sl)] += 1
+    cap = (case.n_steps - info["capture_start"]) / case.n_steps
+    out = {}
+    for name, mask in (("ac", tile_ac), ("gen", ~tile_ac)):
+        fl = fluid & mask
+        el = ~fluid & mask
+        nf, ne = int(fl.sum()), int(el.sum())
+        lf = int(axes_in_layer[fl].sum())
+        le = int(axes_in_layer[el].sum())
+        src_cols = int(mask[info["source_k"]].sum())
+        cls_bytes = int(mask.sum()) / 64
+        suffix = "_ac" if name == "ac" else ""
+        out["velocity" + suffix] = 28 * nf + 49 * ne + 8 * lf + 24 * le + 8 * src_cols + cls_bytes
+        out["stress" + suffix] = 28 * nf + 109 * ne + 8 * lf + 24 * le + 8 * (nf + ne) * cap + cls_bytes
+    out["per_cell_update"] = sum(out[k] for k in KERNELS) / case.cells
+    out["acoustic_fraction"] = float(fluid.mean())
+    out["acoustic_tile_fraction"] = float(tile_ac.mean())
+    return out
 
 
 def load_traffic(kernel: str, workload: str):
@@ -98,7 +114,7 @@ def load_traffic(kernel: str, workload: str):
     return t.get("kernels", {}).get(kernel)
 
 
-def cpu_baseline(case, sample_steps: int = 2) -> dict:
+def cpu_baseline(case, sample_steps: int = 8) -> dict:
     """FP64 oracle on the host cores: full workload grid, one untimed step
     (first touch), then ``sample_steps`` timed steps."""
     import numpy as np
@@ -183,7 +199,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="skull400", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-sweep section")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="override the workload's time-step count (short profiling runs)")
@@ -203,10 +219,17 @@ def main():
         n = 1 << 28                       # 2^28 floats = 1 GiB read + 1 GiB written
         a = torch.ones(n, dtype=torch.float32, device="cuda:0")
         b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "repeats": 5}))
+        ms = e0.elapsed_time(e1) / 5
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "repeats": 6,
+                          "copy_ms": round(ms, 4), "copy_gbs": round(8 * n / ms / 1e6, 1)}))
         return
 
     case = WORKLOADS[args.workload]()
@@ -241,23 +264,28 @@ def main():
     value = args.steps * updates / elapsed / 1e9
 
     # dominant kernel: per-launch HIP events on the launch stream
-    ms_v, ms_s = plan.solve_profiled(mat, src, peak, ws)
+    ms = plan.solve_profiled(mat, src, peak, ws)
     pidx2, _ = plan.status(ws)
     assert pidx2 == pidx
     ab = algorithmic_bytes(case, info, plan.segment_classes(ws))
-    avg = {"velocity": ms_v / case.n_steps, "stress": ms_s / case.n_steps}
-    dom = "stress" if avg["stress"] >= avg["velocity"] else "velocity"
+    avg = {k: m / case.n_steps for k, m in zip(KERNELS, ms)}
+    dom = max(KERNELS, key=lambda k: avg[k])
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
-    log(f"[bench] kernel avg ms: velocity {avg['velocity']:.4f} stress {avg['stress']:.4f}")
+    log("[bench] kernel avg ms: " + ", ".join(f"{k} {avg[k]:.4f}" for k in KERNELS))
     traffic = load_traffic(dom, case.name)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": f"k_{dom}", "avg_launch_ms": round(avg[dom], 5),
             "algorithmic_bytes_per_launch": int(ab[dom]),
-            "algorithmic_bytes_velocity": int(ab["velocity"]),
-            "algorithmic_bytes_stress": int(ab["stress"]),
+            "kernels": {f"k_{k}": {"avg_launch_ms": round(avg[k], 5),
+                                   "algorithmic_bytes": int(ab[k]),
+                                   "achieved_gbs": round(ab[k] / (avg[k] * 1e-3) / 1e9, 1)
+                                   if avg[k] > 0 else None} for k in KERNELS},
+            "step_achieved_gbs": round(sum(ab[k] for k in KERNELS)
+                                       / (sum(avg.values()) * 1e-3) / 1e9, 1),
             "bytes_per_cell_update": round(ab["per_cell_update"], 2),
-            "acoustic_cell_fraction": round(ab["acoustic_fraction"], 4)}
+            "acoustic_cell_fraction": round(ab["acoustic_fraction"], 4),
+            "acoustic_tile_cell_fraction": round(ab["acoustic_tile_fraction"], 4)}
 
     out = {
         "metric": "Gcell-updates/s",

@@ -78,6 +78,8 @@ typedef struct {
   int32_t capture_start, source_k, pitch;
   uint64_t workspace_bytes;   /* device workspace a solve needs */
   uint64_t cells;             /* nx * ny * nz */
+  int32_t tile_rows;          /* step-kernel tile: 64 x tile_rows x tile_planes cells */
+  int32_t tile_planes;
 } bbfd_plan_info;
 
 typedef struct bbfd_plan bbfd_plan;
@@ -85,7 +87,9 @@ typedef struct bbfd_plan bbfd_plan;
 /* Validates the problem and derives, in FP64 on the host, the per-material
    Zener constants (Q from Eq. 3 times qc, one relaxation mechanism at the drive
    frequency), the time step and the absorbing-layer profile; packs them as the
-   FP32 device tables.  *out is NULL on failure. */
+   FP32 device tables.  *out is NULL on failure.  BBFD_EINVAL also when a
+   padded field array would exceed 4 GiB (about 1e9 cells): the step kernels
+   address arrays by 32-bit byte offsets. */
 int bbfd_plan_create(const bbfd_problem *problem, bbfd_plan **out);
 int bbfd_plan_get_info(const bbfd_plan *plan, bbfd_plan_info *out);
 void bbfd_plan_destroy(bbfd_plan *plan);
@@ -141,9 +145,13 @@ int bbfd_solve_direct(const bbfd_plan *plan, const uint8_t *mat, const float *sr
 
 /* Profiling variant of bbfd_solve_direct: records a HIP event before and after
    every kernel of the time loop on stream, waits for the solve, and writes the
-   summed kernel times in milliseconds: ms_out[0] = velocity update (Eq. 1 rows
-   1-3), ms_out[1] = stress/memory update (rows 4-9).  Results are identical to
-   bbfd_solve. */
+   summed kernel times in milliseconds to ms_out[0..3]: the velocity update
+   (Eq. 1 rows 1-3) of the acoustic tiles [0] and of the general tiles [1],
+   the stress/memory update (rows 4-9) of the acoustic tiles [2] and of the
+   general tiles [3].  A tile (64 x tile_rows x tile_planes cells, see
+   bbfd_plan_info) is acoustic when every one of its row segments is of a
+   lossless-fluid class (bbfd_segment_classes) on every plane; it then runs
+   kernels specialised to that case.  Results are identical to bbfd_solve. */
 int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
                         float *peak, void *workspace, uint64_t workspace_bytes, void *stream,
                         double *ms_out);

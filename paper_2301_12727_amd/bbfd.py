@@ -47,7 +47,8 @@ class PlanInfo(C.Structure):
     _fields_ = [("dx", C.c_double), ("dt", C.c_double), ("c_max", C.c_double),
                 ("steps_per_period", C.c_int32), ("capture_start", C.c_int32),
                 ("source_k", C.c_int32), ("pitch", C.c_int32),
-                ("workspace_bytes", C.c_uint64), ("cells", C.c_uint64)]
+                ("workspace_bytes", C.c_uint64), ("cells", C.c_uint64),
+                ("tile_rows", C.c_int32), ("tile_planes", C.c_int32)]
 
 
 EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
@@ -204,14 +205,16 @@ class Plan:
 
     def solve_profiled(self, mat, src, peak, ws, stream=None):
         """Direct-launch solve with per-kernel HIP events on the launch stream;
-        returns (velocity ms, stress ms) summed over the time loop."""
-        out = np.zeros(2, dtype=np.float64)
+        returns the summed milliseconds of the four step kernels over the time
+        loop: (acoustic velocity, general velocity, acoustic stress, general
+        stress)."""
+        out = np.zeros(4, dtype=np.float64)
         _check(lib().bbfd_solve_profiled(self.h, C.c_void_p(mat.data_ptr()),
                                          C.c_void_p(src.data_ptr()), C.c_void_p(peak.data_ptr()),
                                          C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                          C.c_void_p(_stream(stream)),
                                          out.ctypes.data_as(C.c_void_p)))
-        return float(out[0]), float(out[1])
+        return tuple(float(v) for v in out)
 
     def status(self, ws, stream=None):
         """Synchronise and return (peak_index, peak_value); raises on device errors."""

@@ -1,7 +1,8 @@
 """Build libbbfd.so (HIP, gfx950) in-tree with hipcc.
 
 Every HIP translation unit is compiled with packed FP32 instructions disabled
-(``-Xclang -target-feature -Xclang -packed-fp32-ops``).
+(``-Xclang -target-feature -Xclang -packed-fp32-ops``); the step kernels also
+without floating-point contraction.
 """
 import os
 import subprocess
@@ -15,6 +16,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbbfd.so")
 
 SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip", "surrogate.cpp", "nn.hip"]
+# The step kernels spell out every fused multiply-add (fmaf) and must not get
+# others from the compiler: every code path then rounds a cell identically.
+EXTRA = {"fdtd.hip": ["-ffp-contract=off"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -24,7 +28,7 @@ FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -21,9 +21,14 @@
 #include "bbfd_dev.h"
 
 namespace bbfd {
-hipError_t launch_step(const StepArgs &a, hipStream_t s);
-hipError_t launch_velocity(const StepArgs &a, hipStream_t s);
-hipError_t launch_stress(const StepArgs &a, hipStream_t s);
+hipError_t launch_velocity(const StepArgs &a, const int *const *lists, const int *counts,
+                           int which, hipStream_t s);
+hipError_t launch_stress(const StepArgs &a, const int *const *lists, const int *counts, int which,
+                         hipStream_t s);
+hipError_t launch_tile_lists(const StepArgs &a, uint8_t *kind, int *const *lists, int *counts,
+                             hipStream_t s);
+hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tiles, int by,
+                              hipStream_t s);
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
                        hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
@@ -103,7 +108,9 @@ struct bbfd_plan {
   int nseg = 1;
   int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
-         off_cls = 0, off_state = 0, off_psi = 0, ws_bytes = 0;
+         off_cls = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
+         ws_bytes = 0;
+  int n_tiles = 0;
   std::mutex mu;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -269,6 +276,10 @@ void layout(bbfd_plan *pl) {
   pl->nseg = (p.nx + kSeg - 1) / kSeg;
   pl->kpad = (int)round_up((size_t)p.nz, 4) + 4;
   pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
+  pl->n_tiles = pl->nseg * (int)((p.ny + kRows - 1) / kRows) * ((p.nz + pl->kchunk - 1) / pl->kchunk);
+  pl->off_kind = o; o += round_up((size_t)pl->n_tiles, 256);
+  pl->off_lists = o; o += round_up(2 * (size_t)pl->n_tiles * sizeof(int), 256);
+  pl->off_counts = o; o += 256;
   pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
   pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
   pl->ws_bytes = o;
@@ -306,7 +317,7 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.relax_b = pl->relax_b;
   a.kchunk = pl->kchunk;
   a.nby = (pl->prob.ny + kRows - 1) / kRows;
-  a.n_tiles = pl->nseg * a.nby * ((pl->prob.nz + pl->kchunk - 1) / pl->kchunk);
+  a.n_tiles = pl->n_tiles;
   return a;
 }
 
@@ -358,6 +369,11 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
   if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_cls), pl->g,
                            pl->nseg, pl->kpad, (const float *)(ws + pl->off_lut), s)) != hipSuccess)
     return hip_fail(e, "segment classes");
+  StepArgs a = step_args(pl, mat, nullptr, peak, ws);
+  int *lists[2] = {(int *)(ws + pl->off_lists), (int *)(ws + pl->off_lists) + pl->n_tiles};
+  if ((e = launch_tile_lists(a, (uint8_t *)(ws + pl->off_kind), lists, (int *)(ws + pl->off_counts),
+                             s)) != hipSuccess)
+    return hip_fail(e, "tile lists");
   return BBFD_OK;
 }
 
@@ -371,7 +387,9 @@ int enqueue_epilogue(const bbfd_plan *pl, float *peak, char *ws, hipStream_t s) 
 }
 
 // Enqueue one whole solve on s (no synchronisation).  With ev != NULL (direct
-// launches only), ev[2n] / ev[2n+1] / ev[2n+2] bracket step n's two kernels.
+// launches only), ev[4n + q] / ev[4n + q + 1] bracket kernel q of step n
+// (q: 0 acoustic velocity, 1 general velocity, 2 acoustic stress, 3 general
+// stress), ev[4 n_steps] closes the last one.
 int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
                   char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
   const bbfd_problem &p = pl->prob;
@@ -379,20 +397,20 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
   if (rc) return rc;
   hipError_t e;
   StepArgs a = step_args(pl, mat, src, peak, ws);
+  const int *lists[2] = {(const int *)(ws + pl->off_lists),
+                         (const int *)(ws + pl->off_lists) + pl->n_tiles};
+  const int *counts = (const int *)(ws + pl->off_counts);
   for (int n = 0; n < p.n_steps; ++n) {
     a.src_c = pl->src_c[n];
     a.src_s = pl->src_s[n];
     a.capture = (n + 1 >= pl->cap) ? 1 : 0;
-    if (ev) {
-      (void)hipEventRecord(ev[2 * n], s);
-      if ((e = launch_velocity(a, s)) != hipSuccess) return hip_fail(e, "velocity launch");
-      (void)hipEventRecord(ev[2 * n + 1], s);
-      if ((e = launch_stress(a, s)) != hipSuccess) return hip_fail(e, "stress launch");
-    } else if ((e = launch_step(a, s)) != hipSuccess) {
-      return hip_fail(e, "step launch");
+    for (int q = 0; q < 4; ++q) {
+      if (ev) (void)hipEventRecord(ev[4 * n + q], s);
+      e = q < 2 ? launch_velocity(a, lists, counts, q, s) : launch_stress(a, lists, counts, q - 2, s);
+      if (e != hipSuccess) return hip_fail(e, q < 2 ? "velocity launch" : "stress launch");
     }
   }
-  if (ev) (void)hipEventRecord(ev[2 * p.n_steps], s);
+  if (ev) (void)hipEventRecord(ev[4 * p.n_steps], s);
   return enqueue_epilogue(pl, peak, ws, s);
 }
 
@@ -488,6 +506,14 @@ int bbfd_plan_create(const bbfd_problem *problem, bbfd_plan **out) {
     return rc;
   }
   layout(pl);
+  // the step kernels address every array by 32-bit byte offsets
+  const uint64_t cells = (uint64_t)problem->nx * problem->ny * problem->nz;
+  if ((uint64_t)pl->g.stride * sizeof(float) > 0xffffffffull ||
+      cells * sizeof(float) > 0xffffffffull) {
+    bbfd_plan_destroy(pl);
+    return fail(BBFD_EINVAL, "grid of %llu cells exceeds the 4 GiB per-array limit of the step kernels",
+                (unsigned long long)cells);
+  }
   *out = pl;
   return BBFD_OK;
 }
@@ -513,6 +539,8 @@ int bbfd_plan_get_info(const bbfd_plan *pl, bbfd_plan_info *out) {
   out->pitch = pl->g.pitch;
   out->workspace_bytes = pl->ws_bytes;
   out->cells = (uint64_t)pl->prob.nx * pl->prob.ny * pl->prob.nz;
+  out->tile_rows = kRows;
+  out->tile_planes = pl->kchunk;
   return BBFD_OK;
 }
 
@@ -603,7 +631,7 @@ int bbfd_solve_profiled(const bbfd_plan *cpl, const uint8_t *mat, const float *s
     if ((rc = ensure_pinned(pl))) return rc;
   }
   const int n = pl->prob.n_steps;
-  std::vector<hipEvent_t> ev(2 * (size_t)n + 1, nullptr);
+  std::vector<hipEvent_t> ev(4 * (size_t)n + 1, nullptr);
   hipError_t e = hipSuccess;
   for (auto &x : ev)
     if ((e = hipEventCreate(&x)) != hipSuccess) break;
@@ -612,19 +640,16 @@ int bbfd_solve_profiled(const bbfd_plan *cpl, const uint8_t *mat, const float *s
     rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, s, ev.data());
     if (rc == BBFD_OK && (e = hipEventSynchronize(ev.back())) != hipSuccess)
       rc = hip_fail(e, "profiled solve sync");
-    double tv = 0.0, ts = 0.0;
-    for (int k = 0; rc == BBFD_OK && k < n; ++k) {
-      float a = 0.f, b = 0.f;
-      if (hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]) != hipSuccess ||
-          hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2]) != hipSuccess) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; rc == BBFD_OK && k < 4 * n; ++k) {
+      float a = 0.f;
+      if (hipEventElapsedTime(&a, ev[k], ev[k + 1]) != hipSuccess) {
         rc = fail(BBFD_EHIP, "event timing");
         break;
       }
-      tv += a;
-      ts += b;
+      t[k % 4] += a;
     }
-    ms_out[0] = tv;
-    ms_out[1] = ts;
+    for (int q = 0; q < 4; ++q) ms_out[q] = t[q];
   } else {
     rc = hip_fail(e, "event create");
   }
@@ -835,6 +860,9 @@ int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *
     int rc = enqueue_prologue(b->plans[q], mat[q], peak[q], ws + b->sub_off[q], s);
     if (rc) return rc;
   }
+  if ((e = launch_batch_kinds((const StepArgs *)(ws + b->off_desc), (BatchTile *)(ws + b->off_tiles),
+                              (int)b->tiles.size(), b->by, s)) != hipSuccess)
+    return hip_fail(e, "batch tile kinds");
   const int last = steps < 0 ? b->max_steps : std::min(steps, b->max_steps);
   for (int k = 0; k < last; ++k)
     if ((e = launch_batched_step(b->by, (const StepArgs *)(ws + b->off_desc),

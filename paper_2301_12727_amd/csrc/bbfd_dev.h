@@ -99,7 +99,8 @@ struct BatchTile {
   int solve;
   int bx, by;   // x segment and row-block index inside the solve
   int k0, k1;   // z range
-  int pad[3];
+  int kind;     // 1: acoustic tile (set on the device once the classes are known)
+  int pad[2];
 };
 
 // Device status block at the front of the workspace.

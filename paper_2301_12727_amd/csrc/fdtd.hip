@@ -20,22 +20,30 @@
 
 namespace bbfd {
 
+// Every floating-point operation of a cell update is spelled out here and in
+// the helpers below (fused multiply-adds only where written as fmaf: this
+// file is compiled with -ffp-contract=off), and every code path (general
+// tiles, acoustic tiles, register windows, batched tiles) goes through the
+// same helpers, so a cell's value does not depend on which kernel or tiling
+// updated it.
+
 #define C1 (9.0f / 8.0f)
 #define C2 (-1.0f / 24.0f)
-// 4th-order staggered differences (times dx): forward one sits at +1/2 of the
-// centre sample, backward one at the centre from samples stored at +1/2.
-#define DP(a, c, s) (C1 * ((a)[(c) + (s)] - (a)[(c)]) + C2 * ((a)[(c) + 2 * (s)] - (a)[(c) - (s)]))
-#define DM(a, c, s) (C1 * ((a)[(c)] - (a)[(c) - (s)]) + C2 * ((a)[(c) + (s)] - (a)[(c) - 2 * (s)]))
+// 4th-order staggered differences (times dx) from four samples: the forward
+// one sits at +1/2 of sample p0, the backward one at p0 from samples stored
+// at +1/2.
+__device__ __forceinline__ float dfw(float m1, float p0, float p1, float p2) {
+  return fmaf(C1, p1 - p0, C2 * (p2 - m1));
+}
+__device__ __forceinline__ float dbw(float m2, float m1, float p0, float p1) {
+  return fmaf(C1, p0 - m1, C2 * (p1 - m2));
+}
+// Source force on a v_z face: c Re S - s Im S.
+__device__ __forceinline__ float src_force(float c, float s, float2 q) {
+  return fmaf(c, q.x, -(s * q.y));
+}
 
 typedef __attribute__((address_space(4))) const uint32_t ScalarU32;
-
-// CPML memory update and corrected derivative: psi <- b psi + a d, d + psi.
-__device__ __forceinline__ float cpml_apply(float *__restrict__ psi, long long c, float &q, float b,
-                                            float a, float d) {
-  q = b * q + a * d;
-  psi[c] = q;
-  return d + q;
-}
 
 __device__ __forceinline__ bool in_layer(int i, int n, int L) { return i < L || i >= n - L; }
 
@@ -72,10 +80,32 @@ struct ClassColumn {
   }
 };
 
+// Element access by 32-bit byte offset from a uniform base: the loads and
+// stores take the scalar-base + 32-bit vector-offset addressing form, so each
+// neighbour costs one 32-bit register (x and, for pitches up to 1023 floats, y
+// neighbours fold into the instruction's immediate offset).
+__device__ __forceinline__ float ldb(const float *base, uint32_t off) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ __forceinline__ void stb(float *base, uint32_t off, float v) {
+  *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + off) = v;
+}
+__device__ __forceinline__ float cpml_b(float *psi, uint32_t off, float q, float b, float a, float d) {
+  q = fmaf(b, q, a * d);
+  stb(psi, off, q);
+  return d + q;
+}
+
 // Every cell update below first issues all of its loads (stencil values, own
 // state, layer memories, material indices) and only then computes and
 // stores, so a wave has one round trip to memory per cell instead of a chain
-// of load-wait-store steps.
+// of load-wait-store steps.  Addresses are 32-bit byte offsets from uniform
+// bases (see ldb).
+
+#define DPB(a, o, s4) dfw(ldb(a, (o) - (s4)), ldb(a, o), ldb(a, (o) + (s4)), ldb(a, (o) + 2 * (s4)))
+#define DMB(a, o, s4) dbw(ldb(a, (o) - 2 * (s4)), ldb(a, (o) - (s4)), ldb(a, o), ldb(a, (o) + (s4)))
+
+__device__ __forceinline__ int ldi(const uint8_t *idx, uint32_t off) { return idx[off]; }
 
 // Velocity update (Eq. 1 rows 1-3) of one tile: x segment bx (one cell per
 // lane), row j (wave-uniform), planes [k0, k1); lut is the LDS copy of the
@@ -84,86 +114,79 @@ struct ClassColumn {
 // jump of 2 S across z = (ks + 1/2) dx.
 __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lut, int bx, int j,
                                               int k0, int k1, float src_c, float src_s) {
-  const Grid g = A.g;
+  const Grid &g = A.g;
   const int i = bx * kSeg + threadIdx.x;
   if (i >= g.nx || j >= g.ny) return;
-  const long long P = g.pitch, PL = g.plane;
-  const float *__restrict__ sxx = A.f[SXX], *__restrict__ syy = A.f[SYY];
-  const float *__restrict__ szz = A.f[SZZ], *__restrict__ sxy = A.f[SXY];
-  const float *__restrict__ sxz = A.f[SXZ], *__restrict__ syz = A.f[SYZ];
-  float *__restrict__ vx = A.f[VX], *__restrict__ vy = A.f[VY], *__restrict__ vz = A.f[VZ];
-  float *__restrict__ p0 = A.psi[0], *__restrict__ p1 = A.psi[1], *__restrict__ p2 = A.psi[2];
-  float *__restrict__ p3 = A.psi[3], *__restrict__ p4 = A.psi[4], *__restrict__ p5 = A.psi[5];
-  float *__restrict__ p6 = A.psi[6], *__restrict__ p7 = A.psi[7], *__restrict__ p8 = A.psi[8];
-  const uint8_t *__restrict__ idx = A.idx;
-  const float2 *__restrict__ srcp = A.src + (long long)j * g.nx + i;
+  const uint32_t P = (uint32_t)g.pitch, PL = (uint32_t)g.plane, P4 = 4 * P, PL4 = 4 * PL;
+  const float *sxx = A.f[SXX], *syy = A.f[SYY], *szz = A.f[SZZ];
+  const float *sxy = A.f[SXY], *sxz = A.f[SXZ], *syz = A.f[SYZ];
+  float *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
+  const uint8_t *idx = A.idx;
+  const uint32_t so = (uint32_t)(j * g.nx + i) * 8u;
   const bool px = in_layer(i, g.nx, g.L), py = in_layer(j, g.ny, g.L);
   const float4 tx = px ? A.pml.x[i] : make_float4(1.f, 0.f, 1.f, 0.f);
   const float4 ty = py ? A.pml.y[j] : make_float4(1.f, 0.f, 1.f, 0.f);
   ClassColumn col(A, j, bx, k0);
-  for (int k = k0; k < k1; ++k) {
-    const long long c = g.off(i, j, k);
+  uint32_t c = (uint32_t)g.off(i, j, k0);
+  for (int k = k0; k < k1; ++k, c += PL) {
+    const uint32_t o = 4 * c;
     const bool pz = in_layer(k, g.nz, g.L);
     const bool on_src = k == g.ks;
     const int cl = col.at(k, k0);
+    const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+    float2 sq = make_float2(0.f, 0.f);
+    if (on_src) sq = *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(A.src) + so);
     if (cl) {
       // acoustic path: the three normal stresses are equal and the shear
       // stresses vanish throughout the stencil's reach
-      float d1 = DP(sxx, c, 1), e2 = DP(sxx, c, P), f3 = DP(sxx, c, PL);
-      const float vxo = vx[c], vyo = vy[c], vzo = vz[c];
-      float q0 = 0.f, q4 = 0.f, q8 = 0.f;
-      if (px) q0 = p0[c];
-      if (py) q4 = p4[c];
-      if (pz) q8 = p8[c];
-      float2 sq = make_float2(0.f, 0.f);
-      if (on_src) sq = *srcp;
-      const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+      float d1 = DPB(sxx, o, 4), e2 = DPB(sxx, o, P4), f3 = DPB(sxx, o, PL4);
+      const float vxo = ldb(vx, o), vyo = ldb(vy, o), vzo = ldb(vz, o);
+      const float q0 = px ? ldb(A.psi[0], o) : 0.f;
+      const float q4 = py ? ldb(A.psi[4], o) : 0.f;
+      const float q8 = pz ? ldb(A.psi[8], o) : 0.f;
       const float b = 1.f / lut[(cl - 1) * kLutW + kRhoS];
-      if (px) d1 = cpml_apply(p0, c, q0, tx.z, tx.w, d1);
-      if (py) e2 = cpml_apply(p4, c, q4, ty.z, ty.w, e2);
-      if (pz) f3 = cpml_apply(p8, c, q8, tz.z, tz.w, f3);
-      vx[c] = vxo + b * d1;
-      vy[c] = vyo + b * e2;
-      if (on_src) f3 += src_c * sq.x - src_s * sq.y;
-      vz[c] = vzo + b * f3;
+      if (px) d1 = cpml_b(A.psi[0], o, q0, tx.z, tx.w, d1);
+      if (py) e2 = cpml_b(A.psi[4], o, q4, ty.z, ty.w, e2);
+      if (pz) f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
+      stb(vx, o, fmaf(b, d1, vxo));
+      stb(vy, o, fmaf(b, e2, vyo));
+      if (on_src) f3 += src_force(src_c, src_s, sq);
+      stb(vz, o, fmaf(b, f3, vzo));
       continue;
     }
-    const int m0 = idx[c], mx = idx[c + 1], my = idx[c + P], mz = idx[c + PL];
-    float d1 = DP(sxx, c, 1), d2 = DM(sxy, c, P), d3 = DM(sxz, c, PL);
-    float e1 = DM(sxy, c, 1), e2 = DP(syy, c, P), e3 = DM(syz, c, PL);
-    float f1 = DM(sxz, c, 1), f2 = DM(syz, c, P), f3 = DP(szz, c, PL);
-    const float vxo = vx[c], vyo = vy[c], vzo = vz[c];
+    const int m0 = ldi(idx, c), mx = ldi(idx, c + 1), my = ldi(idx, c + P), mz = ldi(idx, c + PL);
+    float d1 = DPB(sxx, o, 4), d2 = DMB(sxy, o, P4), d3 = DMB(sxz, o, PL4);
+    float e1 = DMB(sxy, o, 4), e2 = DPB(syy, o, P4), e3 = DMB(syz, o, PL4);
+    float f1 = DMB(sxz, o, 4), f2 = DMB(syz, o, P4), f3 = DPB(szz, o, PL4);
+    const float vxo = ldb(vx, o), vyo = ldb(vy, o), vzo = ldb(vz, o);
     float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f, q4 = 0.f, q5 = 0.f, q6 = 0.f, q7 = 0.f, q8 = 0.f;
-    if (px) { q0 = p0[c]; q3 = p3[c]; q6 = p6[c]; }
-    if (py) { q1 = p1[c]; q4 = p4[c]; q7 = p7[c]; }
-    if (pz) { q2 = p2[c]; q5 = p5[c]; q8 = p8[c]; }
-    float2 sq = make_float2(0.f, 0.f);
-    if (on_src) sq = *srcp;
-    const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+    if (px) { q0 = ldb(A.psi[0], o); q3 = ldb(A.psi[3], o); q6 = ldb(A.psi[6], o); }
+    if (py) { q1 = ldb(A.psi[1], o); q4 = ldb(A.psi[4], o); q7 = ldb(A.psi[7], o); }
+    if (pz) { q2 = ldb(A.psi[2], o); q5 = ldb(A.psi[5], o); q8 = ldb(A.psi[8], o); }
     const float r0 = lut[m0 * kLutW + kRhoS];
     const float bx = 2.f / (r0 + lut[mx * kLutW + kRhoS]);
     const float by = 2.f / (r0 + lut[my * kLutW + kRhoS]);
     const float bz = 2.f / (r0 + lut[mz * kLutW + kRhoS]);
     if (px) {
-      d1 = cpml_apply(p0, c, q0, tx.z, tx.w, d1);
-      e1 = cpml_apply(p3, c, q3, tx.x, tx.y, e1);
-      f1 = cpml_apply(p6, c, q6, tx.x, tx.y, f1);
+      d1 = cpml_b(A.psi[0], o, q0, tx.z, tx.w, d1);
+      e1 = cpml_b(A.psi[3], o, q3, tx.x, tx.y, e1);
+      f1 = cpml_b(A.psi[6], o, q6, tx.x, tx.y, f1);
     }
     if (py) {
-      d2 = cpml_apply(p1, c, q1, ty.x, ty.y, d2);
-      e2 = cpml_apply(p4, c, q4, ty.z, ty.w, e2);
-      f2 = cpml_apply(p7, c, q7, ty.x, ty.y, f2);
+      d2 = cpml_b(A.psi[1], o, q1, ty.x, ty.y, d2);
+      e2 = cpml_b(A.psi[4], o, q4, ty.z, ty.w, e2);
+      f2 = cpml_b(A.psi[7], o, q7, ty.x, ty.y, f2);
     }
     if (pz) {
-      d3 = cpml_apply(p2, c, q2, tz.x, tz.y, d3);
-      e3 = cpml_apply(p5, c, q5, tz.x, tz.y, e3);
-      f3 = cpml_apply(p8, c, q8, tz.z, tz.w, f3);
+      d3 = cpml_b(A.psi[2], o, q2, tz.x, tz.y, d3);
+      e3 = cpml_b(A.psi[5], o, q5, tz.x, tz.y, e3);
+      f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
     }
-    vx[c] = vxo + bx * (d1 + d2 + d3);
-    vy[c] = vyo + by * (e1 + e2 + e3);
+    stb(vx, o, fmaf(bx, d1 + d2 + d3, vxo));
+    stb(vy, o, fmaf(by, e1 + e2 + e3, vyo));
     float fz = f1 + f2 + f3;
-    if (on_src) fz += src_c * sq.x - src_s * sq.y;  // traction source on the v_z faces of plane ks
-    vz[c] = vzo + bz * fz;
+    if (on_src) fz += src_force(src_c, src_s, sq);  // traction source on the v_z faces of plane ks
+    stb(vz, o, fmaf(bz, fz, vzo));
   }
 }
 
@@ -172,7 +195,7 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
 // mean of the old and new memory value (all pre-scaled by dt).
 __device__ __forceinline__ float zener(float &s, float &r, float elastic, float target, float ra,
                                        float rb) {
-  const float rn = ra * r - rb * target;
+  const float rn = fmaf(ra, r, -(rb * target));
   s += elastic + 0.5f * (r + rn);
   r = rn;
   return s;
@@ -188,94 +211,87 @@ __device__ __forceinline__ void edge(float &s, float &r, float e, float2 a, floa
                                      float2 d, float ra, float rb) {
   const float mue = 4.f / (a.x + b.x + c.x + d.x);
   const float te = 0.25f * (a.y + b.y + c.y + d.y);
-  zener(s, r, mue * (1.f + te) * e, mue * te * e, ra, rb);
+  zener(s, r, (mue * (1.f + te)) * e, (mue * te) * e, ra, rb);
 }
 
-__device__ __forceinline__ void capture_peak(float *__restrict__ peak, long long q, float old,
-                                             float s3) {
-  const float a = fabsf(s3) / 3.f;
-  if (a > old || a != a) peak[q] = a;
-}
 
 // Stress + memory update (Eq. 1 rows 4-9) and peak capture of one tile;
 // capture is this step's flag.
 __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut, int bx, int j,
                                             int k0, int k1, int capture) {
-  const Grid g = A.g;
+  const Grid &g = A.g;
   const int i = bx * kSeg + threadIdx.x;
   if (i >= g.nx || j >= g.ny) return;
-  const long long P = g.pitch, PL = g.plane;
-  const float *__restrict__ vx = A.f[VX], *__restrict__ vy = A.f[VY], *__restrict__ vz = A.f[VZ];
-  float *__restrict__ sxxp = A.f[SXX], *__restrict__ syyp = A.f[SYY], *__restrict__ szzp = A.f[SZZ];
-  float *__restrict__ sxyp = A.f[SXY], *__restrict__ sxzp = A.f[SXZ], *__restrict__ syzp = A.f[SYZ];
-  float *__restrict__ rxxp = A.f[RXX], *__restrict__ ryyp = A.f[RYY], *__restrict__ rzzp = A.f[RZZ];
-  float *__restrict__ rxyp = A.f[RXY], *__restrict__ rxzp = A.f[RXZ], *__restrict__ ryzp = A.f[RYZ];
-  float *__restrict__ p9 = A.psi[9], *__restrict__ p10 = A.psi[10], *__restrict__ p11 = A.psi[11];
-  float *__restrict__ p12 = A.psi[12], *__restrict__ p13 = A.psi[13], *__restrict__ p14 = A.psi[14];
-  float *__restrict__ p15 = A.psi[15], *__restrict__ p16 = A.psi[16], *__restrict__ p17 = A.psi[17];
-  float *__restrict__ peak = A.peak;
-  const uint8_t *__restrict__ idx = A.idx;
+  const uint32_t P = (uint32_t)g.pitch, PL = (uint32_t)g.plane, P4 = 4 * P, PL4 = 4 * PL;
+  const uint32_t QL4 = (uint32_t)(g.ny * g.nx) * 4u;
+  const float *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
+  float *sxxp = A.f[SXX], *syyp = A.f[SYY], *szzp = A.f[SZZ];
+  float *sxyp = A.f[SXY], *sxzp = A.f[SXZ], *syzp = A.f[SYZ];
+  float *rxxp = A.f[RXX], *ryyp = A.f[RYY], *rzzp = A.f[RZZ];
+  float *rxyp = A.f[RXY], *rxzp = A.f[RXZ], *ryzp = A.f[RYZ];
+  const uint8_t *idx = A.idx;
   const float ra = A.relax_a, rb = A.relax_b;
   const bool px = in_layer(i, g.nx, g.L), py = in_layer(j, g.ny, g.L);
   const float4 tx = px ? A.pml.x[i] : make_float4(1.f, 0.f, 1.f, 0.f);
   const float4 ty = py ? A.pml.y[j] : make_float4(1.f, 0.f, 1.f, 0.f);
   ClassColumn col(A, j, bx, k0);
-  for (int k = k0; k < k1; ++k) {
-    const long long c = g.off(i, j, k);
-    const long long q = ((long long)k * g.ny + j) * g.nx + i;
+  uint32_t c = (uint32_t)g.off(i, j, k0);
+  uint32_t qo = ((uint32_t)k0 * (uint32_t)(g.ny * g.nx) + (uint32_t)(j * g.nx + i)) * 4u;
+  for (int k = k0; k < k1; ++k, c += PL, qo += QL4) {
+    const uint32_t o = 4 * c;
     const bool pz = in_layer(k, g.nz, g.L);
     const int cl = col.at(k, k0);
+    const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+    const float pk = capture ? ldb(A.peak, qo) : 0.f;
     if (cl) {
       // acoustic path: only the (equal) normal stresses change
-      float exx = DM(vx, c, 1), eyy = DM(vy, c, P), ezz = DM(vz, c, PL);
-      const float so = sxxp[c];
-      float q9 = 0.f, q10 = 0.f, q11 = 0.f, pk = 0.f;
-      if (px) q9 = p9[c];
-      if (py) q10 = p10[c];
-      if (pz) q11 = p11[c];
-      if (capture) pk = peak[q];
-      const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
-      if (px) exx = cpml_apply(p9, c, q9, tx.x, tx.y, exx);
-      if (py) eyy = cpml_apply(p10, c, q10, ty.x, ty.y, eyy);
-      if (pz) ezz = cpml_apply(p11, c, q11, tz.x, tz.y, ezz);
-      const float sn = so + lut[(cl - 1) * kLutW + kPiU] * (exx + eyy + ezz);
-      sxxp[c] = sn;
-      syyp[c] = sn;
-      szzp[c] = sn;
-      if (capture) capture_peak(peak, q, pk, sn + sn + sn);
+      float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = DMB(vz, o, PL4);
+      const float so = ldb(sxxp, o);
+      const float q9 = px ? ldb(A.psi[9], o) : 0.f;
+      const float q10 = py ? ldb(A.psi[10], o) : 0.f;
+      const float q11 = pz ? ldb(A.psi[11], o) : 0.f;
+      if (px) exx = cpml_b(A.psi[9], o, q9, tx.x, tx.y, exx);
+      if (py) eyy = cpml_b(A.psi[10], o, q10, ty.x, ty.y, eyy);
+      if (pz) ezz = cpml_b(A.psi[11], o, q11, tz.x, tz.y, ezz);
+      const float sn = fmaf(lut[(cl - 1) * kLutW + kPiU], exx + eyy + ezz, so);
+      stb(sxxp, o, sn);
+      stb(syyp, o, sn);
+      stb(szzp, o, sn);
+      if (capture) {
+        const float a = fabsf(sn + sn + sn) / 3.f;
+        if (a > pk || a != a) stb(A.peak, qo, a);
+      }
       continue;
     }
-    const int m0 = idx[c], mx = idx[c + 1], my = idx[c + P], mz = idx[c + PL];
-    const int mxy = idx[c + 1 + P], mxz = idx[c + 1 + PL], myz = idx[c + P + PL];
-    float exx = DM(vx, c, 1), eyy = DM(vy, c, P), ezz = DM(vz, c, PL);
-    float dyvx = DP(vx, c, P), dxvy = DP(vy, c, 1);
-    float dzvx = DP(vx, c, PL), dxvz = DP(vz, c, 1);
-    float dzvy = DP(vy, c, PL), dyvz = DP(vz, c, P);
-    float sxx = sxxp[c], syy = syyp[c], szz = szzp[c];
-    float rxx = rxxp[c], ryy = ryyp[c], rzz = rzzp[c];
-    float sxy = sxyp[c], sxz = sxzp[c], syz = syzp[c];
-    float rxy = rxyp[c], rxz = rxzp[c], ryz = ryzp[c];
+    const int m0 = ldi(idx, c), mx = ldi(idx, c + 1), my = ldi(idx, c + P), mz = ldi(idx, c + PL);
+    const int mxy = ldi(idx, c + 1 + P), mxz = ldi(idx, c + 1 + PL), myz = ldi(idx, c + P + PL);
+    float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = DMB(vz, o, PL4);
+    float dyvx = DPB(vx, o, P4), dxvy = DPB(vy, o, 4);
+    float dzvx = DPB(vx, o, PL4), dxvz = DPB(vz, o, 4);
+    float dzvy = DPB(vy, o, PL4), dyvz = DPB(vz, o, P4);
+    float sxx = ldb(sxxp, o), syy = ldb(syyp, o), szz = ldb(szzp, o);
+    float rxx = ldb(rxxp, o), ryy = ldb(ryyp, o), rzz = ldb(rzzp, o);
+    float sxy = ldb(sxyp, o), sxz = ldb(sxzp, o), syz = ldb(syzp, o);
+    float rxy = ldb(rxyp, o), rxz = ldb(rxzp, o), ryz = ldb(ryzp, o);
     float q9 = 0.f, q10 = 0.f, q11 = 0.f, q12 = 0.f, q13 = 0.f, q14 = 0.f, q15 = 0.f, q16 = 0.f,
-          q17 = 0.f, pk = 0.f;
-    if (px) { q9 = p9[c]; q13 = p13[c]; q15 = p15[c]; }
-    if (py) { q10 = p10[c]; q12 = p12[c]; q17 = p17[c]; }
-    if (pz) { q11 = p11[c]; q14 = p14[c]; q16 = p16[c]; }
-    if (capture) pk = peak[q];
-    const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+          q17 = 0.f;
+    if (px) { q9 = ldb(A.psi[9], o); q13 = ldb(A.psi[13], o); q15 = ldb(A.psi[15], o); }
+    if (py) { q10 = ldb(A.psi[10], o); q12 = ldb(A.psi[12], o); q17 = ldb(A.psi[17], o); }
+    if (pz) { q11 = ldb(A.psi[11], o); q14 = ldb(A.psi[14], o); q16 = ldb(A.psi[16], o); }
     if (px) {
-      exx = cpml_apply(p9, c, q9, tx.x, tx.y, exx);
-      dxvy = cpml_apply(p13, c, q13, tx.z, tx.w, dxvy);
-      dxvz = cpml_apply(p15, c, q15, tx.z, tx.w, dxvz);
+      exx = cpml_b(A.psi[9], o, q9, tx.x, tx.y, exx);
+      dxvy = cpml_b(A.psi[13], o, q13, tx.z, tx.w, dxvy);
+      dxvz = cpml_b(A.psi[15], o, q15, tx.z, tx.w, dxvz);
     }
     if (py) {
-      eyy = cpml_apply(p10, c, q10, ty.x, ty.y, eyy);
-      dyvx = cpml_apply(p12, c, q12, ty.z, ty.w, dyvx);
-      dyvz = cpml_apply(p17, c, q17, ty.z, ty.w, dyvz);
+      eyy = cpml_b(A.psi[10], o, q10, ty.x, ty.y, eyy);
+      dyvx = cpml_b(A.psi[12], o, q12, ty.z, ty.w, dyvx);
+      dyvz = cpml_b(A.psi[17], o, q17, ty.z, ty.w, dyvz);
     }
     if (pz) {
-      ezz = cpml_apply(p11, c, q11, tz.x, tz.y, ezz);
-      dzvx = cpml_apply(p14, c, q14, tz.z, tz.w, dzvx);
-      dzvy = cpml_apply(p16, c, q16, tz.z, tz.w, dzvy);
+      ezz = cpml_b(A.psi[11], o, q11, tz.x, tz.y, ezz);
+      dzvx = cpml_b(A.psi[14], o, q14, tz.z, tz.w, dzvx);
+      dzvy = cpml_b(A.psi[16], o, q16, tz.z, tz.w, dzvy);
     }
     const float4 L0 = *reinterpret_cast<const float4 *>(lut + m0 * kLutW);  // piU muU piTau muTau
     const float th = exx + eyy + ezz;
@@ -283,22 +299,174 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
       const float piu = L0.x, muu2 = 2.f * L0.y;
       const float pit = L0.z, mut2 = 2.f * L0.w;
       float lat = eyy + ezz;
-      zener(sxx, rxx, piu * th - muu2 * lat, pit * th - mut2 * lat, ra, rb);
+      zener(sxx, rxx, fmaf(piu, th, -(muu2 * lat)), fmaf(pit, th, -(mut2 * lat)), ra, rb);
       lat = exx + ezz;
-      zener(syy, ryy, piu * th - muu2 * lat, pit * th - mut2 * lat, ra, rb);
+      zener(syy, ryy, fmaf(piu, th, -(muu2 * lat)), fmaf(pit, th, -(mut2 * lat)), ra, rb);
       lat = exx + eyy;
-      zener(szz, rzz, piu * th - muu2 * lat, pit * th - mut2 * lat, ra, rb);
+      zener(szz, rzz, fmaf(piu, th, -(muu2 * lat)), fmaf(pit, th, -(mut2 * lat)), ra, rb);
     }
     const float2 e0 = edge_in(lut, m0), ex = edge_in(lut, mx);
     const float2 ey = edge_in(lut, my), ez = edge_in(lut, mz);
     edge(sxy, rxy, dyvx + dxvy, e0, ex, ey, edge_in(lut, mxy), ra, rb);
     edge(sxz, rxz, dzvx + dxvz, e0, ex, ez, edge_in(lut, mxz), ra, rb);
     edge(syz, ryz, dzvy + dyvz, e0, ey, ez, edge_in(lut, myz), ra, rb);
-    sxxp[c] = sxx; syyp[c] = syy; szzp[c] = szz;
-    rxxp[c] = rxx; ryyp[c] = ryy; rzzp[c] = rzz;
-    sxyp[c] = sxy; sxzp[c] = sxz; syzp[c] = syz;
-    rxyp[c] = rxy; rxzp[c] = rxz; ryzp[c] = ryz;
-    if (capture) capture_peak(peak, q, pk, sxx + syy + szz);
+    stb(sxxp, o, sxx); stb(syyp, o, syy); stb(szzp, o, szz);
+    stb(rxxp, o, rxx); stb(ryyp, o, ryy); stb(rzzp, o, rzz);
+    stb(sxyp, o, sxy); stb(sxzp, o, sxz); stb(syzp, o, syz);
+    stb(rxyp, o, rxy); stb(rxzp, o, rxz); stb(ryzp, o, ryz);
+    if (capture) {
+      const float a = fabsf(sxx + syy + szz) / 3.f;
+      if (a > pk || a != a) stb(A.peak, qo, a);
+    }
+  }
+}
+
+// ------------------------------------------------------------ acoustic tiles
+// A tile whose every row segment is of a lossless-fluid class on every plane
+// of its chunk runs these leaner kernels: no index map, no shear or memory
+// state, and the z-neighbours of the one z-differenced field held in a
+// register window (one new plane loaded per step in z), at a fraction of the
+// general kernels' registers.  The arithmetic is the acoustic branch of the
+// general tile code, operation for operation.
+
+struct AcCtx {
+  const StepArgs *A;
+  uint32_t P4, PL4;  // row and plane strides in bytes
+  bool px, py;
+  float4 tx, ty;
+};
+
+// One plane of the acoustic velocity update at byte offset o.  z0..z3: sxx at
+// planes k-1, k, k+1, k+2 of this column.
+struct VelAc {
+  float xm, xp, xp2, ym, yp, yp2, vx, vy, vz, q0, q4, q8;
+  float2 sq;
+  float4 tz;
+  int cl;
+  bool pz, src;
+  __device__ __forceinline__ void load(const AcCtx &C, uint32_t o, int k, int cls, uint32_t so) {
+    const StepArgs &A = *C.A;
+    const float *sxx = A.f[SXX];
+    cl = cls;
+    pz = in_layer(k, A.g.nz, A.g.L);
+    src = k == A.g.ks;
+    xm = ldb(sxx, o - 4); xp = ldb(sxx, o + 4); xp2 = ldb(sxx, o + 8);
+    ym = ldb(sxx, o - C.P4); yp = ldb(sxx, o + C.P4); yp2 = ldb(sxx, o + 2 * C.P4);
+    vx = ldb(A.f[VX], o); vy = ldb(A.f[VY], o); vz = ldb(A.f[VZ], o);
+    q0 = C.px ? ldb(A.psi[0], o) : 0.f;
+    q4 = C.py ? ldb(A.psi[4], o) : 0.f;
+    q8 = pz ? ldb(A.psi[8], o) : 0.f;
+    tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+    sq = src ? *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(A.src) + so)
+             : make_float2(0.f, 0.f);
+  }
+  __device__ __forceinline__ void finish(const AcCtx &C, const float *lut, uint32_t o, float z0,
+                                         float z1, float z2, float z3, float src_c, float src_s) {
+    const StepArgs &A = *C.A;
+    float d1 = dfw(xm, z1, xp, xp2), e2 = dfw(ym, z1, yp, yp2), f3 = dfw(z0, z1, z2, z3);
+    const float b = 1.f / lut[(cl - 1) * kLutW + kRhoS];
+    if (C.px) d1 = cpml_b(A.psi[0], o, q0, C.tx.z, C.tx.w, d1);
+    if (C.py) e2 = cpml_b(A.psi[4], o, q4, C.ty.z, C.ty.w, e2);
+    if (pz) f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
+    stb(A.f[VX], o, fmaf(b, d1, vx));
+    stb(A.f[VY], o, fmaf(b, e2, vy));
+    if (src) f3 += src_force(src_c, src_s, sq);
+    stb(A.f[VZ], o, fmaf(b, f3, vz));
+  }
+};
+
+__device__ __forceinline__ bool ac_setup(AcCtx &C, const StepArgs &A, int i, int j) {
+  const Grid &g = A.g;
+  if (i >= g.nx || j >= g.ny) return false;
+  C.A = &A;
+  C.P4 = (uint32_t)g.pitch * 4u;
+  C.PL4 = (uint32_t)g.plane * 4u;
+  C.px = in_layer(i, g.nx, g.L);
+  C.py = in_layer(j, g.ny, g.L);
+  C.tx = C.px ? A.pml.x[i] : make_float4(1.f, 0.f, 1.f, 0.f);
+  C.ty = C.py ? A.pml.y[j] : make_float4(1.f, 0.f, 1.f, 0.f);
+  return true;
+}
+
+__device__ __forceinline__ void velocity_ac_tile(const StepArgs &A, const float *lut, int bx, int j,
+                                                 int k0, int k1, float src_c, float src_s) {
+  const int i = bx * kSeg + threadIdx.x;
+  AcCtx C;
+  if (!ac_setup(C, A, i, j)) return;
+  const float *sxx = A.f[SXX];
+  const uint32_t so = (uint32_t)(j * A.g.nx + i) * 8u;
+  ClassColumn col(A, j, bx, k0);
+  uint32_t o = (uint32_t)A.g.off(i, j, k0) * 4u;
+  float z0 = ldb(sxx, o - C.PL4), z1 = ldb(sxx, o), z2 = ldb(sxx, o + C.PL4),
+        z3 = ldb(sxx, o + 2 * C.PL4);
+  int k = k0;
+  for (; k < k1; ++k, o += C.PL4) {
+    VelAc a;
+    a.load(C, o, k, col.at(k, k0), so);
+    const float h = (k + 1 < k1) ? ldb(sxx, o + 3 * C.PL4) : 0.f;    // plane k + 3, if used
+    a.finish(C, lut, o, z0, z1, z2, z3, src_c, src_s);
+    z0 = z1; z1 = z2; z2 = z3; z3 = h;
+  }
+}
+
+// One plane of the acoustic stress update.  w0..w3: vz at planes k-2, k-1,
+// k, k+1 of this column.
+struct StrAc {
+  float xm2, xm1, x0, xp1, ym2, ym1, y0, yp1, s, q9, q10, q11, pk;
+  float4 tz;
+  int cl;
+  bool pz;
+  __device__ __forceinline__ void load(const AcCtx &C, uint32_t o, uint32_t qo, int k, int cls,
+                                       int capture) {
+    const StepArgs &A = *C.A;
+    const float *vx = A.f[VX], *vy = A.f[VY];
+    cl = cls;
+    pz = in_layer(k, A.g.nz, A.g.L);
+    xm2 = ldb(vx, o - 8); xm1 = ldb(vx, o - 4); x0 = ldb(vx, o); xp1 = ldb(vx, o + 4);
+    ym2 = ldb(vy, o - 2 * C.P4); ym1 = ldb(vy, o - C.P4); y0 = ldb(vy, o); yp1 = ldb(vy, o + C.P4);
+    s = ldb(A.f[SXX], o);
+    q9 = C.px ? ldb(A.psi[9], o) : 0.f;
+    q10 = C.py ? ldb(A.psi[10], o) : 0.f;
+    q11 = pz ? ldb(A.psi[11], o) : 0.f;
+    tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
+    pk = capture ? ldb(A.peak, qo) : 0.f;
+  }
+  __device__ __forceinline__ void finish(const AcCtx &C, const float *lut, uint32_t o, uint32_t qo,
+                                         float w0, float w1, float w2, float w3, int capture) {
+    const StepArgs &A = *C.A;
+    float exx = dbw(xm2, xm1, x0, xp1), eyy = dbw(ym2, ym1, y0, yp1), ezz = dbw(w0, w1, w2, w3);
+    if (C.px) exx = cpml_b(A.psi[9], o, q9, C.tx.x, C.tx.y, exx);
+    if (C.py) eyy = cpml_b(A.psi[10], o, q10, C.ty.x, C.ty.y, eyy);
+    if (pz) ezz = cpml_b(A.psi[11], o, q11, tz.x, tz.y, ezz);
+    const float sn = fmaf(lut[(cl - 1) * kLutW + kPiU], exx + eyy + ezz, s);
+    stb(A.f[SXX], o, sn);
+    stb(A.f[SYY], o, sn);
+    stb(A.f[SZZ], o, sn);
+    if (capture) {
+      const float a = fabsf(sn + sn + sn) / 3.f;
+      if (a > pk || a != a) stb(A.peak, qo, a);
+    }
+  }
+};
+
+__device__ __forceinline__ void stress_ac_tile(const StepArgs &A, const float *lut, int bx, int j,
+                                               int k0, int k1, int capture) {
+  const int i = bx * kSeg + threadIdx.x;
+  AcCtx C;
+  if (!ac_setup(C, A, i, j)) return;
+  const float *vz = A.f[VZ];
+  const uint32_t QL4 = (uint32_t)(A.g.ny * A.g.nx) * 4u;
+  ClassColumn col(A, j, bx, k0);
+  uint32_t o = (uint32_t)A.g.off(i, j, k0) * 4u;
+  uint32_t qo = ((uint32_t)k0 * (uint32_t)(A.g.ny * A.g.nx) + (uint32_t)(j * A.g.nx + i)) * 4u;
+  float w0 = ldb(vz, o - 2 * C.PL4), w1 = ldb(vz, o - C.PL4), w2 = ldb(vz, o), w3 = ldb(vz, o + C.PL4);
+  int k = k0;
+  for (; k < k1; ++k, o += C.PL4, qo += QL4) {
+    StrAc a;
+    a.load(C, o, qo, k, col.at(k, k0), capture);
+    const float h = ldb(vz, o + 2 * C.PL4);  // plane k + 2 <= nz + 1
+    a.finish(C, lut, o, qo, w0, w1, w2, w3, capture);
+    w0 = w1; w1 = w2; w2 = w3; w3 = h;
   }
 }
 
@@ -317,20 +485,110 @@ __device__ __forceinline__ int wave_row() { return __builtin_amdgcn_readfirstlan
 // Dynamic LDS of the step kernels: the material table, n_mat * kLutW floats.
 extern __shared__ __align__(16) float s_lut[];
 
-__global__ void __launch_bounds__(kSeg * kRows) k_velocity(StepArgs A) {
+// Single-solve step kernels.  The tiles of a solve are split once per solve
+// into two lists (acoustic / general, each in tile order); block b of a
+// launch takes list entry xcd_band(b, count) and blocks beyond the list's
+// length exit at once.
+__global__ void __launch_bounds__(kSeg * kRows)
+    k_velocity(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
+  const int n = *count;
+  if ((int)blockIdx.x >= n) return;
   stage_lut(s_lut, A.lut, A.n_mat);
   __syncthreads();
   int bx, by, k0, k1;
-  tile_coords(A, xcd_band(blockIdx.x, gridDim.x), bx, by, k0, k1);
+  tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
   velocity_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
 }
 
-__global__ void __launch_bounds__(kSeg * kRows) k_stress(StepArgs A) {
+__global__ void __launch_bounds__(kSeg * kRows)
+    k_stress(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
+  const int n = *count;
+  if ((int)blockIdx.x >= n) return;
   stage_lut(s_lut, A.lut, A.n_mat);
   __syncthreads();
   int bx, by, k0, k1;
-  tile_coords(A, xcd_band(blockIdx.x, gridDim.x), bx, by, k0, k1);
+  tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
   stress_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.capture);
+}
+
+__global__ void __launch_bounds__(kSeg * kRows)
+    k_velocity_ac(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
+  const int n = *count;
+  if ((int)blockIdx.x >= n) return;
+  stage_lut(s_lut, A.lut, A.n_mat);
+  __syncthreads();
+  int bx, by, k0, k1;
+  tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
+  velocity_ac_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
+}
+
+__global__ void __launch_bounds__(kSeg * kRows)
+    k_stress_ac(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
+  const int n = *count;
+  if ((int)blockIdx.x >= n) return;
+  stage_lut(s_lut, A.lut, A.n_mat);
+  __syncthreads();
+  int bx, by, k0, k1;
+  tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
+  stress_ac_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.capture);
+}
+
+// Tile kinds of a single solve: 1 when every row segment of the tile has a
+// fluid class on every plane of its chunk (acoustic tile), else 0.
+__global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A.n_tiles; t += gridDim.x * blockDim.x) {
+    int bx, by, k0, k1;
+    tile_coords(A, t, bx, by, k0, k1);
+    bool ac = true;
+    for (int r = 0; ac && r < kRows; ++r) {
+      const int j = by * kRows + r;
+      if (j >= A.g.ny) break;
+      const uint8_t *colp = A.cls + ((long long)j * A.nseg + bx) * A.kpad;
+      for (int k = k0; k < k1; ++k)
+        if (colp[k] == 0) {
+          ac = false;
+          break;
+        }
+    }
+    kind[t] = ac ? 1 : 0;
+  }
+}
+
+// Stable split of the tile ids by kind: lists[0] acoustic, lists[1] general,
+// counts[0..1] their lengths.  One block; a chunked block-wide prefix sum.
+constexpr int kListThreads = 1024;
+__global__ void __launch_bounds__(kListThreads)
+    k_tile_lists(const uint8_t *__restrict__ kind, int n, int *__restrict__ list_ac,
+                 int *__restrict__ list_gen, int *__restrict__ counts) {
+  __shared__ int sc[kListThreads];
+  __shared__ int base;
+  const int t = threadIdx.x;
+  if (t == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += kListThreads) {
+    const int id = c0 + t;
+    const int f = (id < n && kind[id]) ? 1 : 0;
+    sc[t] = f;
+    __syncthreads();
+    for (int o = 1; o < kListThreads; o <<= 1) {  // inclusive Hillis-Steele scan
+      const int v = t >= o ? sc[t - o] : 0;
+      __syncthreads();
+      sc[t] += v;
+      __syncthreads();
+    }
+    const int before = base + sc[t] - f;  // acoustic tiles before id
+    if (id < n) {
+      if (f) list_ac[before] = id;
+      else list_gen[id - before] = id;
+    }
+    __syncthreads();
+    if (t == kListThreads - 1) base += sc[t];
+    __syncthreads();
+  }
+  if (t == 0) {
+    counts[0] = base;
+    counts[1] = n - base;
+  }
 }
 
 // Persistent batched step kernels: a fixed grid walks the live prefix of the
@@ -352,7 +610,11 @@ __global__ void __launch_bounds__(kSeg * BY)
       staged = tl.solve;
     }
     const float2 cs = coef[(long long)tl.solve * max_steps + n];
-    velocity_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x, cs.y);
+    if (tl.kind)
+      velocity_ac_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x,
+                       cs.y);
+    else
+      velocity_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x, cs.y);
   }
 }
 
@@ -370,8 +632,32 @@ __global__ void __launch_bounds__(kSeg * BY)
       __syncthreads();
       staged = tl.solve;
     }
-    stress_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1,
-                (n + 1 >= cap[tl.solve]) ? 1 : 0);
+    const int capture = (n + 1 >= cap[tl.solve]) ? 1 : 0;
+    if (tl.kind)
+      stress_ac_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, capture);
+    else
+      stress_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, capture);
+  }
+}
+
+// Kinds of the batch tile table (rows of by rows each), as k_tile_kinds.
+__global__ void k_batch_kinds(const StepArgs *__restrict__ desc, BatchTile *__restrict__ tiles,
+                              int n_tiles, int by) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) {
+    BatchTile &tl = tiles[t];
+    const StepArgs &A = desc[tl.solve];
+    bool ac = true;
+    for (int r = 0; ac && r < by; ++r) {
+      const int j = tl.by * by + r;
+      if (j >= A.g.ny) break;
+      const uint8_t *colp = A.cls + ((long long)j * A.nseg + tl.bx) * A.kpad;
+      for (int k = tl.k0; k < tl.k1; ++k)
+        if (colp[k] == 0) {
+          ac = false;
+          break;
+        }
+    }
+    tl.kind = ac ? 1 : 0;
   }
 }
 
@@ -532,20 +818,47 @@ __global__ void __launch_bounds__(kRedThreads)
 
 static size_t lut_bytes(int n_mat) { return (size_t)n_mat * kLutW * sizeof(float); }
 
-hipError_t launch_velocity(const StepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_velocity, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a);
+// lists: [0] acoustic tile ids, [1] general tile ids (n_tiles ints each);
+// counts: their lengths (device).  Each launch has n_tiles blocks.
+hipError_t launch_velocity(const StepArgs &a, const int *const *lists, const int *counts,
+                           int which, hipStream_t s) {
+  if (which == 0)
+    hipLaunchKernelGGL(k_velocity_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s,
+                       a, lists[0], counts);
+  else
+    hipLaunchKernelGGL(k_velocity, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a,
+                       lists[1], counts + 1);
   return hipGetLastError();
 }
 
-hipError_t launch_stress(const StepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_stress, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a);
+hipError_t launch_stress(const StepArgs &a, const int *const *lists, const int *counts, int which,
+                         hipStream_t s) {
+  if (which == 0)
+    hipLaunchKernelGGL(k_stress_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s,
+                       a, lists[0], counts);
+  else
+    hipLaunchKernelGGL(k_stress, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a,
+                       lists[1], counts + 1);
   return hipGetLastError();
 }
 
-hipError_t launch_step(const StepArgs &a, hipStream_t s) {
-  hipError_t e = launch_velocity(a, s);
-  if (e != hipSuccess) return e;
-  return launch_stress(a, s);
+hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tiles, int by,
+                              hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  int blocks = (n_tiles + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_batch_kinds, dim3(blocks), dim3(256), 0, s, desc, tiles, n_tiles, by);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_lists(const StepArgs &a, uint8_t *kind, int *const *lists, int *counts,
+                             hipStream_t s) {
+  int blocks = (a.n_tiles + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_tile_kinds, dim3(blocks), dim3(256), 0, s, a, kind);
+  hipLaunchKernelGGL(k_tile_lists, dim3(1), dim3(kListThreads), 0, s, kind, a.n_tiles, lists[0],
+                     lists[1], counts);
+  return hipGetLastError();
 }
 
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,

@@ -36,6 +36,16 @@ def batch_inputs(b, cases, ws):
     return mats, srcs, peaks
 
 
+def assert_same_map(got, ref, idx, val, ref_idx, ref_val, what):
+    """Batched and single solves tile the grid differently, so a lossless-fluid
+    cell may be updated by the acoustic-tile kernels in one and by the general
+    kernels' acoustic branch in the other.  Both spell out the same operations
+    (no compiler contraction in the step kernels), so the maps are identical
+    bit for bit."""
+    assert np.array_equal(got, ref), (what, float(np.abs(got.astype(np.float64) - ref).max()))
+    assert idx == ref_idx and val == ref_val, what
+
+
 def test_batched_equals_single_solves(tmp_path):
     cases = uneven_cases()
     say("[batch] sizes " + ", ".join(f"{c.nx}x{c.ny}x{c.nz}/{c.n_steps}" for c in cases))
@@ -55,16 +65,16 @@ def test_batched_equals_single_solves(tmp_path):
         for i, c in enumerate(cases):
             idx, val = b.status(ws, i)
             got = peaks[i].cpu().numpy()
-            assert np.array_equal(got, single[i][0]), (shape, i)
-            assert idx == single[i][1] and val == single[i][2]
+            assert_same_map(got, single[i][0], idx, val, single[i][1], single[i][2], (shape, i))
     cache = str(tmp_path / "tune.txt")
     best, shape = b.autotune(mats, srcs, peaks, ws, cache_path=cache, probe_steps=3)
     say(f"[batch] autotuned shape {shape}, {best:.3f} ms per 3 steps")
     assert best > 0 and os.path.exists(cache)
     b.solve(mats, srcs, peaks, ws)
     for i in range(len(cases)):
-        b.status(ws, i)
-        assert np.array_equal(peaks[i].cpu().numpy(), single[i][0])
+        idx, val = b.status(ws, i)
+        assert_same_map(peaks[i].cpu().numpy(), single[i][0], idx, val, single[i][1],
+                        single[i][2], ("tuned", i))
     # a second batch of the same size class reads the cached shape
     b2 = bb.Batch(cases)
     ws2 = b2.workspace()
