@@ -64,7 +64,9 @@ def algorithmic_bytes(case, info, classes) -> dict:
                 and written (8 B each).  Source plane: 8 B per column.
       stress,   elastic cell: read 3 velocities + 6 stresses + 6 memories +
                 index, write 6 + 6 = 109 B; acoustic cell: read 3 velocities +
-                1 normal stress, write 3 normal stresses = 28 B.  Layer memories
+                1 normal stress, write 3 normal stresses = 28 B, or only sigma_xx
+                (20 B) in an acoustic tile where no elastic segment within 2 rows
+                or planes reads sigma_yy / sigma_zz (keep flag).  Layer memories
                 as above.  Capture steps add 8 B/cell (peak read + write)."""
     import numpy as np
     nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
@@ -77,6 +79,20 @@ def algorithmic_bytes(case, info, classes) -> dict:
     kind = pad.reshape(nzc, K, nby, R, nseg).all(axis=(1, 3))      # acoustic tiles
     tile_ac = np.repeat(np.repeat(np.repeat(kind, K, 0)[:nz], R, 1)[:, :ny], 64, 2)[:, :, :nx]
     fluid = np.repeat(seg, 64, axis=2)[:, :, :nx]
+    # keep flags: an acoustic segment within 2 rows or 2 planes of an elastic
+    # (class 0) segment of the same x segment stores sigma_yy and sigma_zz too
+    el = ~seg
+    near = np.zeros_like(el)
+    for d in (-2, -1, 0, 1):
+        if d < 0:
+            near[:, -d:] |= el[:, :d]
+            near[-d:] |= el[:d]
+        elif d > 0:
+            near[:, :-d] |= el[:, d:]
+            near[:-d] |= el[d:]
+        else:
+            near |= el
+    keep = np.repeat(near, 64, axis=2)[:, :, :nx]
     axes_in_layer = np.zeros((nz, ny, nx), dtype=np.int8)
     for a, n in ((2, nx), (1, ny), (0, nz)):
         sl = [slice(None)] * 3
@@ -94,7 +110,10 @@ def algorithmic_bytes(case, info, classes) -> dict:
         cls_bytes = int(mask.sum()) / 64
         suffix = "_ac" if name == "ac" else ""
         out["velocity" + suffix] = 28 * nf + 49 * ne + 8 * lf + 24 * le + 8 * src_cols + cls_bytes
-        out["stress" + suffix] = 28 * nf + 109 * ne + 8 * lf + 24 * le + 8 * (nf + ne) * cap + cls_bytes
+        # acoustic tiles store sigma_yy, sigma_zz only where kept (20 B otherwise)
+        nk = int((fl & keep).sum()) if name == "ac" else nf
+        out["stress" + suffix] = (20 * nf + 8 * nk + 109 * ne + 8 * lf + 24 * le
+                                  + 8 * (nf + ne) * cap + cls_bytes * (2 if name == "ac" else 1))
     out["per_cell_update"] = sum(out[k] for k in KERNELS) / case.cells
     out["acoustic_fraction"] = float(fluid.mean())
     out["acoustic_tile_fraction"] = float(tile_ac.mean())

@@ -177,11 +177,13 @@ int bbfd_segment_classes(const bbfd_plan *plan, const void *workspace, uint8_t *
                          uint64_t n, void *stream);
 
 /* ---- Batched sweeps: many independent solves of uneven size in one launch.
-   Each problem keeps its own grid, frequency, time step, tables and step count;
-   a persistent pair of kernels per time step walks a ragged (solve, tile)
-   table, solves dropping out of it once their own step count is reached, and
-   the whole sweep is captured in one HIP graph.  Results equal those of the
-   same problems solved one by one with bbfd_solve. */
+   Each problem keeps its own grid, frequency, time step, tables and step count.
+   Per time step, four kernels (velocity and stress, each for acoustic and for
+   general tiles) walk ragged per-kind (solve, tile) tables ordered by
+   decreasing step count, so solves drop out of them once their own step count
+   is reached; the blocks are persistent or one per tile (autotuned), and the
+   whole sweep is captured in one HIP graph.  Results equal those of the same
+   problems solved one by one with bbfd_solve, bit for bit. */
 typedef struct bbfd_batch bbfd_batch;
 
 /* Creates one plan per problem (same validation and errors as
@@ -190,14 +192,16 @@ int bbfd_batch_create(const bbfd_problem *problems, int32_t n, bbfd_batch **out)
 void bbfd_batch_destroy(bbfd_batch *batch);
 /* workspace_bytes: device workspace of a batched solve (all solves plus the
    tile/descriptor tables).  shape (may be NULL, 4 ints): rows per block,
-   persistent blocks, z cells per tile, number of tiles. */
+   persistent blocks (0: one block per tile), z cells per tile, number of
+   tiles. */
 int bbfd_batch_info(const bbfd_batch *batch, uint64_t *workspace_bytes, int32_t *shape);
 /* Plan of solve i (owned by the batch) and the byte offset of its part of the
    batch workspace, e.g. for bbfd_source_rayleigh on that solve. */
 const bbfd_plan *bbfd_batch_plan(const bbfd_batch *batch, int32_t i);
 uint64_t bbfd_batch_offset(const bbfd_batch *batch, int32_t i);
-/* Launch shape: by in {1, 2, 4, 8} rows per 64-wide block, blocks >= 1
-   persistent blocks, kchunk >= 1 z cells per tile (>= 4 when by = 1). */
+/* Launch shape: by in {1, 2, 4, 8} rows per 64-wide block; blocks >= 1
+   persistent blocks, or 0 for one block per tile; kchunk >= 1 z cells per
+   tile (>= 4 when by = 1). */
 int bbfd_batch_set_shape(bbfd_batch *batch, int32_t by, int32_t blocks, int32_t kchunk);
 /* mat, src, peak: host arrays of n device pointers (layouts as bbfd_solve).
    Captures on first use per pointer set and launch shape; enqueued on stream. */

@@ -32,16 +32,18 @@ hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tile
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
                        hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
-hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, const Grid &g, int nseg, int kpad,
-                           const float *lut, hipStream_t s);
+hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, uint8_t *keep, const Grid &g, int nseg,
+                           int kpad, const float *lut, hipStream_t s);
 hipError_t launch_argmax(const float *P, int nx, int ny, int nz, int L, float *pv, long long *pi,
                          Status *st, hipStream_t s);
 int argmax_partials();
 hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, int planes, double dx,
                            double z0, double kw, double pre, float2 *out, hipStream_t s);
-hipError_t launch_batched_step(int by, const StepArgs *desc, const BatchTile *tiles, int n_tiles,
-                               const float2 *coef, const int *cap, int max_steps, int n,
-                               int blocks, int max_mat, hipStream_t s);
+hipError_t launch_batched_step(int by, const BatchWalk *W, const float2 *coef, const int *cap,
+                               int max_steps, int n, int blocks, int max_mat, hipStream_t s);
+hipError_t launch_batch_split(const BatchTile *tiles, int n, const int *solve_end, int n_solves,
+                              int *table_ac, int *table_gen, int *scan, int *len_ac, int *len_gen,
+                              hipStream_t s);
 }  // namespace bbfd
 
 using namespace bbfd;
@@ -108,7 +110,7 @@ struct bbfd_plan {
   int nseg = 1;
   int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
-         off_cls = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
+         off_cls = 0, off_keep = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
          ws_bytes = 0;
   int n_tiles = 0;
   std::mutex mu;
@@ -276,6 +278,7 @@ void layout(bbfd_plan *pl) {
   pl->nseg = (p.nx + kSeg - 1) / kSeg;
   pl->kpad = (int)round_up((size_t)p.nz, 4) + 4;
   pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
+  pl->off_keep = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->n_tiles = pl->nseg * (int)((p.ny + kRows - 1) / kRows) * ((p.nz + pl->kchunk - 1) / pl->kchunk);
   pl->off_kind = o; o += round_up((size_t)pl->n_tiles, 256);
   pl->off_lists = o; o += round_up(2 * (size_t)pl->n_tiles * sizeof(int), 256);
@@ -301,6 +304,7 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.cls = (const uint8_t *)(ws + pl->off_cls);
   a.nseg = pl->nseg;
   a.kpad = pl->kpad;
+  a.keep = (const uint8_t *)(ws + pl->off_keep);
   a.lut = (const float *)(ws + pl->off_lut);
   a.n_mat = pl->prob.n_materials;
   const float4 *t = (const float4 *)(ws + pl->off_pml);
@@ -366,8 +370,9 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
   if ((e = launch_pack(mat, (uint8_t *)(ws + pl->off_idx), pl->g, p.n_materials, &st->flags, s)) !=
       hipSuccess)
     return hip_fail(e, "index pack");
-  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_cls), pl->g,
-                           pl->nseg, pl->kpad, (const float *)(ws + pl->off_lut), s)) != hipSuccess)
+  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_cls),
+                           (uint8_t *)(ws + pl->off_keep), pl->g, pl->nseg, pl->kpad,
+                           (const float *)(ws + pl->off_lut), s)) != hipSuccess)
     return hip_fail(e, "segment classes");
   StepArgs a = step_args(pl, mat, nullptr, peak, ws);
   int *lists[2] = {(int *)(ws + pl->off_lists), (int *)(ws + pl->off_lists) + pl->n_tiles};
@@ -735,18 +740,21 @@ struct bbfd_batch {
   std::vector<bbfd_plan *> plans;
   std::vector<int> order;       // solves by decreasing step count
   std::vector<size_t> sub_off;  // per-solve workspace offset
-  size_t off_desc = 0, off_tiles = 0, off_coef = 0, off_cap = 0, ws_bytes = 0;
+  size_t off_desc = 0, off_tiles = 0, off_coef = 0, off_cap = 0, off_tab = 0, off_scan = 0,
+         off_len = 0, off_end = 0, ws_bytes = 0;
   int max_steps = 0;
   size_t max_tiles = 0;         // capacity of the tile table region
   // launch shape (autotuned): rows per block, persistent blocks, z cells per tile
   int by = 4, blocks = 1024, kchunk = 16;
   int max_mat = 1;              // largest material table (LDS staging size)
   std::vector<BatchTile> tiles;
-  std::vector<int> live;        // live tiles at each step (a prefix of tiles)
+  std::vector<int> solve_end;   // end of each solve's tiles in the table (solve order)
+  std::vector<int> live_solves; // solves still running at each step (a prefix of the order)
   StepArgs *h_desc = nullptr;   // pinned staging, made at the first solve
   BatchTile *h_tiles = nullptr;
   float2 *h_coef = nullptr;
   int *h_cap = nullptr;
+  int *h_end = nullptr;
   std::mutex mu;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -760,7 +768,7 @@ namespace {
 // z cells per tile for a solve: the shape's kchunk, capped at nz.
 void build_tiles(bbfd_batch *b) {
   b->tiles.clear();
-  std::vector<int> end_of_solve;
+  b->solve_end.clear();
   for (int s : b->order) {
     const bbfd_problem &p = b->plans[s]->prob;
     const int kc = std::max(1, std::min(b->kchunk, p.nz));
@@ -776,14 +784,14 @@ void build_tiles(bbfd_batch *b) {
           t.k1 = std::min(k0 + kc, p.nz);
           b->tiles.push_back(t);
         }
-    end_of_solve.push_back((int)b->tiles.size());
+    b->solve_end.push_back((int)b->tiles.size());
   }
-  b->live.assign(b->max_steps, 0);
+  b->live_solves.assign(b->max_steps, 0);
   for (int n = 0; n < b->max_steps; ++n) {
     int live = 0;
     for (size_t q = 0; q < b->order.size(); ++q)
-      if (b->plans[b->order[q]]->prob.n_steps > n) live = end_of_solve[q];
-    b->live[n] = live;
+      if (b->plans[b->order[q]]->prob.n_steps > n) live = (int)q + 1;
+    b->live_solves[n] = live;
   }
 }
 
@@ -811,6 +819,8 @@ int batch_pinned(bbfd_batch *b) {
     return hip_fail(e, "pinned coefficient allocation");
   if ((e = hipHostMalloc((void **)&b->h_cap, n * sizeof(int), hipHostMallocDefault)) != hipSuccess)
     return hip_fail(e, "pinned capture allocation");
+  if ((e = hipHostMalloc((void **)&b->h_end, n * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(e, "pinned tile-range allocation");
   for (size_t s = 0; s < n; ++s) {
     const bbfd_plan *pl = b->plans[s];
     for (int k = 0; k < b->max_steps; ++k) {
@@ -842,19 +852,42 @@ int check_batch_args(const bbfd_batch *b, const uint8_t *const *mat, const float
 
 // Descriptor and table uploads, every solve's prologue, `steps` batched steps
 // (all of them when steps < 0), every solve's epilogue (when complete).
+// Grid of the batched step kernels: the persistent block count, or (blocks =
+// 0) one block per tile of the whole table, an upper bound on either kind's
+// live length.
+int batch_grid(const bbfd_batch *b) {
+  return b->blocks > 0 ? b->blocks : std::max(1, (int)b->tiles.size());
+}
+
+// The two walks (acoustic, general) of step k over the per-kind tables.
+void batch_walks(const bbfd_batch *b, char *ws, int k, BatchWalk *W) {
+  const int *tab = (const int *)(ws + b->off_tab);
+  const int *len = (const int *)(ws + b->off_len);
+  const size_t n = b->plans.size();
+  for (int q = 0; q < 2; ++q) {
+    W[q].desc = (const StepArgs *)(ws + b->off_desc);
+    W[q].tiles = (const BatchTile *)(ws + b->off_tiles);
+    W[q].table = tab + (size_t)q * b->max_tiles;
+    W[q].table_len = len + (size_t)q * (n + 1);
+    W[q].live = b->live_solves[k];
+  }
+}
+
 int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
                   float *const *peak, char *ws, hipStream_t s, int steps = -1) {
   const size_t n = b->plans.size();
   for (size_t q = 0; q < n; ++q)
     b->h_desc[q] = step_args(b->plans[q], mat[q], src[q], peak[q], ws + b->sub_off[q]);
   std::copy(b->tiles.begin(), b->tiles.end(), b->h_tiles);
+  std::copy(b->solve_end.begin(), b->solve_end.end(), b->h_end);
   hipError_t e;
   if ((e = hipMemcpyAsync(ws + b->off_desc, b->h_desc, n * sizeof(StepArgs), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(ws + b->off_tiles, b->h_tiles, b->tiles.size() * sizeof(BatchTile),
                           hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(ws + b->off_coef, b->h_coef, n * (size_t)b->max_steps * sizeof(float2),
                           hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(ws + b->off_cap, b->h_cap, n * sizeof(int), hipMemcpyHostToDevice, s)))
+      (e = hipMemcpyAsync(ws + b->off_cap, b->h_cap, n * sizeof(int), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(ws + b->off_end, b->h_end, n * sizeof(int), hipMemcpyHostToDevice, s)))
     return hip_fail(e, "batch table upload");
   for (size_t q = 0; q < n; ++q) {
     int rc = enqueue_prologue(b->plans[q], mat[q], peak[q], ws + b->sub_off[q], s);
@@ -863,13 +896,22 @@ int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *
   if ((e = launch_batch_kinds((const StepArgs *)(ws + b->off_desc), (BatchTile *)(ws + b->off_tiles),
                               (int)b->tiles.size(), b->by, s)) != hipSuccess)
     return hip_fail(e, "batch tile kinds");
+  {
+    int *tab = (int *)(ws + b->off_tab), *len = (int *)(ws + b->off_len);
+    if ((e = launch_batch_split((const BatchTile *)(ws + b->off_tiles), (int)b->tiles.size(),
+                                (const int *)(ws + b->off_end), (int)n, tab, tab + b->max_tiles,
+                                (int *)(ws + b->off_scan), len, len + n + 1, s)) != hipSuccess)
+      return hip_fail(e, "batch tile split");
+  }
   const int last = steps < 0 ? b->max_steps : std::min(steps, b->max_steps);
-  for (int k = 0; k < last; ++k)
-    if ((e = launch_batched_step(b->by, (const StepArgs *)(ws + b->off_desc),
-                                 (const BatchTile *)(ws + b->off_tiles), b->live[k],
-                                 (const float2 *)(ws + b->off_coef), (const int *)(ws + b->off_cap),
-                                 b->max_steps, k, b->blocks, b->max_mat, s)) != hipSuccess)
+  for (int k = 0; k < last; ++k) {
+    BatchWalk W[2];
+    batch_walks(b, ws, k, W);
+    if ((e = launch_batched_step(b->by, W, (const float2 *)(ws + b->off_coef),
+                                 (const int *)(ws + b->off_cap), b->max_steps, k, batch_grid(b),
+                                 b->max_mat, s)) != hipSuccess)
       return hip_fail(e, "batched step launch");
+  }
   if (steps >= 0) return BBFD_OK;
   for (size_t q = 0; q < n; ++q) {
     int rc = enqueue_epilogue(b->plans[q], peak[q], ws + b->sub_off[q], s);
@@ -927,6 +969,10 @@ int bbfd_batch_create(const bbfd_problem *probs, int32_t n, bbfd_batch **out) {
   b->off_tiles = o; o += round_up(b->max_tiles * sizeof(BatchTile), 256);
   b->off_coef = o; o += round_up((size_t)n * b->max_steps * sizeof(float2), 256);
   b->off_cap = o; o += round_up((size_t)n * sizeof(int), 256);
+  b->off_tab = o; o += round_up(2 * b->max_tiles * sizeof(int), 256);
+  b->off_scan = o; o += round_up(b->max_tiles * sizeof(int), 256);
+  b->off_len = o; o += round_up(2 * ((size_t)n + 1) * sizeof(int), 256);
+  b->off_end = o; o += round_up((size_t)n * sizeof(int), 256);
   for (int s = 0; s < n; ++s) {
     b->sub_off.push_back(o);
     o += round_up(b->plans[s]->ws_bytes, 256);
@@ -945,6 +991,7 @@ void bbfd_batch_destroy(bbfd_batch *b) {
   if (b->h_tiles) (void)hipHostFree(b->h_tiles);
   if (b->h_coef) (void)hipHostFree(b->h_coef);
   if (b->h_cap) (void)hipHostFree(b->h_cap);
+  if (b->h_end) (void)hipHostFree(b->h_end);
   for (bbfd_plan *pl : b->plans) bbfd_plan_destroy(pl);
   delete b;
 }
@@ -976,7 +1023,7 @@ uint64_t bbfd_batch_offset(const bbfd_batch *b, int32_t i) {
 
 int bbfd_batch_set_shape(bbfd_batch *b, int32_t by, int32_t blocks, int32_t kchunk) {
   if (!b) return fail(BBFD_EINVAL, "null batch");
-  if (!(by == 1 || by == 2 || by == 4 || by == 8) || blocks < 1 || kchunk < 1)
+  if (!(by == 1 || by == 2 || by == 4 || by == 8) || blocks < 0 || kchunk < 1)
     return fail(BBFD_EINVAL, "bad launch shape (%d, %d, %d)", by, blocks, kchunk);
   size_t ntiles = 0;
   for (const bbfd_plan *pl : b->plans) {
@@ -1074,8 +1121,8 @@ int bbfd_batch_autotune(bbfd_batch *b, const uint8_t *const *mat, const float *c
   double best = 1e300;
   int bb_ = b->by, bl_ = b->blocks, kc_ = b->kchunk;
   const int bys[] = {1, 2, 4, 8};
-  const int kcs[] = {4, 8, 16, 32, 64};
-  const int bls[] = {512, 1024, 2048, 4096};
+  const int kcs[] = {4, 8, 16, 32};
+  const int bls[] = {0, 1024, 2048, 4096};
   {
     std::lock_guard<std::mutex> lock(b->mu);
     if ((rc = batch_pinned(b))) goto done;
@@ -1092,11 +1139,11 @@ int bbfd_batch_autotune(bbfd_batch *b, const uint8_t *const *mat, const float *c
         if ((rc = enqueue_batch(b, mat, src, peak, (char *)workspace, s, probe_steps))) goto done;
         (void)hipEventRecord(e0, s);
         for (int k = 0; k < probe_steps; ++k) {
-          hipError_t e = launch_batched_step(b->by, (const StepArgs *)((char *)workspace + b->off_desc),
-                                             (const BatchTile *)((char *)workspace + b->off_tiles),
-                                             b->live[k], (const float2 *)((char *)workspace + b->off_coef),
+          BatchWalk W[2];
+          batch_walks(b, (char *)workspace, k, W);
+          hipError_t e = launch_batched_step(b->by, W, (const float2 *)((char *)workspace + b->off_coef),
                                              (const int *)((char *)workspace + b->off_cap), b->max_steps, k,
-                                             b->blocks, b->max_mat, s);
+                                             batch_grid(b), b->max_mat, s);
           if (e != hipSuccess) {
             rc = hip_fail(e, "tuning launch");
             goto done;

@@ -74,6 +74,8 @@ struct StepArgs {
   const uint8_t *cls;     // segment classes, [ny][nseg][kpad]: one z column per segment
   int nseg;               // ceil(nx / kSeg)
   int kpad;               // round_up(nz, 4) + 4 bytes per class column
+  const uint8_t *keep;    // same layout: 1 where an elastic segment reads sigma_yy or
+                          // sigma_zz of this segment (within 2 rows / 2 planes)
   const float *lut;       // kLutW floats per material
   int n_mat;              // materials in lut
   PmlTab pml;
@@ -101,6 +103,15 @@ struct BatchTile {
   int k0, k1;   // z range
   int kind;     // 1: acoustic tile (set on the device once the classes are known)
   int pad[2];
+};
+
+// One persistent batched launch walks the live part of one per-kind tile table.
+struct BatchWalk {
+  const StepArgs *desc;
+  const BatchTile *tiles;
+  const int *table;       // tile indices of one kind, in solve order
+  const int *table_len;   // [live solves] -> live length of table
+  int live;               // solves still running at this step
 };
 
 // Device status block at the front of the workspace.

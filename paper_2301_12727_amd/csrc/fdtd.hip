@@ -43,7 +43,22 @@ __device__ __forceinline__ float src_force(float c, float s, float2 q) {
   return fmaf(c, q.x, -(s * q.y));
 }
 
+// Read-only data the kernels index uniformly, read through the scalar cache.
 typedef __attribute__((address_space(4))) const uint32_t ScalarU32;
+typedef __attribute__((address_space(4))) const int ScalarI32;
+
+// Copy of a uniformly indexed read-only object, dword by dword through the
+// scalar cache.
+template <class T>
+__device__ __forceinline__ T scalar_copy(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized object");
+  T v;
+  const ScalarU32 *src = (const ScalarU32 *)p;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(T) / 4); ++w) dst[w] = src[w];
+  return v;
+}
 
 __device__ __forceinline__ bool in_layer(int i, int n, int L) { return i < L || i >= n - L; }
 
@@ -66,8 +81,9 @@ __device__ __forceinline__ void stage_lut(float *s_lut, const float *lut, int n_
 struct ClassColumn {
   const ScalarU32 *w;
   uint32_t cur, nxt;
-  __device__ __forceinline__ ClassColumn(const StepArgs &A, int j, int seg, int k0) {
-    w = (const ScalarU32 *)(A.cls + ((long long)j * A.nseg + seg) * A.kpad);
+  __device__ __forceinline__ ClassColumn(const StepArgs &A, int j, int seg, int k0,
+                                         const uint8_t *bytes = nullptr) {
+    w = (const ScalarU32 *)((bytes ? bytes : A.cls) + ((long long)j * A.nseg + seg) * A.kpad);
     cur = w[k0 >> 2];
     nxt = w[(k0 >> 2) + 1];
   }
@@ -388,6 +404,10 @@ __device__ __forceinline__ bool ac_setup(AcCtx &C, const StepArgs &A, int i, int
   return true;
 }
 
+// The loads of plane k + 1 are issued before the stores of plane k: the wait
+// for them then does not include the completion of those stores (vector
+// memory operations retire in issue order), so each plane costs about one
+// memory latency instead of a load latency plus a store latency.
 __device__ __forceinline__ void velocity_ac_tile(const StepArgs &A, const float *lut, int bx, int j,
                                                  int k0, int k1, float src_c, float src_s) {
   const int i = bx * kSeg + threadIdx.x;
@@ -399,13 +419,20 @@ __device__ __forceinline__ void velocity_ac_tile(const StepArgs &A, const float 
   uint32_t o = (uint32_t)A.g.off(i, j, k0) * 4u;
   float z0 = ldb(sxx, o - C.PL4), z1 = ldb(sxx, o), z2 = ldb(sxx, o + C.PL4),
         z3 = ldb(sxx, o + 2 * C.PL4);
-  int k = k0;
-  for (; k < k1; ++k, o += C.PL4) {
-    VelAc a;
-    a.load(C, o, k, col.at(k, k0), so);
-    const float h = (k + 1 < k1) ? ldb(sxx, o + 3 * C.PL4) : 0.f;    // plane k + 3, if used
-    a.finish(C, lut, o, z0, z1, z2, z3, src_c, src_s);
+  VelAc cur;
+  cur.load(C, o, k0, col.at(k0, k0), so);
+  float h = (k0 + 1 < k1) ? ldb(sxx, o + 3 * C.PL4) : 0.f;  // plane k0 + 3, if used
+  for (int k = k0; k < k1; ++k, o += C.PL4) {
+    VelAc nxt;
+    float hn = 0.f;
+    if (k + 1 < k1) {
+      nxt.load(C, o + C.PL4, k + 1, col.at(k + 1, k0), so);
+      if (k + 2 < k1) hn = ldb(sxx, o + 4 * C.PL4);          // plane k + 4
+    }
+    cur.finish(C, lut, o, z0, z1, z2, z3, src_c, src_s);
     z0 = z1; z1 = z2; z2 = z3; z3 = h;
+    h = hn;
+    cur = nxt;
   }
 }
 
@@ -414,13 +441,14 @@ __device__ __forceinline__ void velocity_ac_tile(const StepArgs &A, const float 
 struct StrAc {
   float xm2, xm1, x0, xp1, ym2, ym1, y0, yp1, s, q9, q10, q11, pk;
   float4 tz;
-  int cl;
+  int cl, keep;
   bool pz;
   __device__ __forceinline__ void load(const AcCtx &C, uint32_t o, uint32_t qo, int k, int cls,
-                                       int capture) {
+                                       int kp, int capture) {
     const StepArgs &A = *C.A;
     const float *vx = A.f[VX], *vy = A.f[VY];
     cl = cls;
+    keep = kp;
     pz = in_layer(k, A.g.nz, A.g.L);
     xm2 = ldb(vx, o - 8); xm1 = ldb(vx, o - 4); x0 = ldb(vx, o); xp1 = ldb(vx, o + 4);
     ym2 = ldb(vy, o - 2 * C.P4); ym1 = ldb(vy, o - C.P4); y0 = ldb(vy, o); yp1 = ldb(vy, o + C.P4);
@@ -440,8 +468,10 @@ struct StrAc {
     if (pz) ezz = cpml_b(A.psi[11], o, q11, tz.x, tz.y, ezz);
     const float sn = fmaf(lut[(cl - 1) * kLutW + kPiU], exx + eyy + ezz, s);
     stb(A.f[SXX], o, sn);
-    stb(A.f[SYY], o, sn);
-    stb(A.f[SZZ], o, sn);
+    if (keep) {  // read by an elastic neighbour: keep the three normal stresses equal
+      stb(A.f[SYY], o, sn);
+      stb(A.f[SZZ], o, sn);
+    }
     if (capture) {
       const float a = fabsf(sn + sn + sn) / 3.f;
       if (a > pk || a != a) stb(A.peak, qo, a);
@@ -460,13 +490,21 @@ __device__ __forceinline__ void stress_ac_tile(const StepArgs &A, const float *l
   uint32_t o = (uint32_t)A.g.off(i, j, k0) * 4u;
   uint32_t qo = ((uint32_t)k0 * (uint32_t)(A.g.ny * A.g.nx) + (uint32_t)(j * A.g.nx + i)) * 4u;
   float w0 = ldb(vz, o - 2 * C.PL4), w1 = ldb(vz, o - C.PL4), w2 = ldb(vz, o), w3 = ldb(vz, o + C.PL4);
-  int k = k0;
-  for (; k < k1; ++k, o += C.PL4, qo += QL4) {
-    StrAc a;
-    a.load(C, o, qo, k, col.at(k, k0), capture);
-    const float h = ldb(vz, o + 2 * C.PL4);  // plane k + 2 <= nz + 1
-    a.finish(C, lut, o, qo, w0, w1, w2, w3, capture);
+  StrAc cur;
+  ClassColumn kcol(A, j, bx, k0, A.keep);
+  cur.load(C, o, qo, k0, col.at(k0, k0), kcol.at(k0, k0), capture);
+  float h = ldb(vz, o + 2 * C.PL4);  // plane k0 + 2 <= nz + 1
+  for (int k = k0; k < k1; ++k, o += C.PL4, qo += QL4) {
+    StrAc nxt;
+    float hn = 0.f;
+    if (k + 1 < k1) {
+      nxt.load(C, o + C.PL4, qo + QL4, k + 1, col.at(k + 1, k0), kcol.at(k + 1, k0), capture);
+      hn = ldb(vz, o + 3 * C.PL4);  // plane k + 3 <= nz + 1
+    }
+    cur.finish(C, lut, o, qo, w0, w1, w2, w3, capture);
     w0 = w1; w1 = w2; w2 = w3; w3 = h;
+    h = hn;
+    cur = nxt;
   }
 }
 
@@ -591,52 +629,114 @@ __global__ void __launch_bounds__(kListThreads)
   }
 }
 
-// Persistent batched step kernels: a fixed grid walks the live prefix of the
-// (solve, tile) table, each XCD over its own contiguous band of every round;
-// every solve keeps its own grid, tables, step count and source
-// coefficients.  The per-cell arithmetic is the single-solve tile code.
-template <int BY>
+// Batched step kernels: a grid of persistent blocks, or of one block per tile
+// (when the grid is at least as long as the table), walks the live part of
+// one of the two per-kind tile tables (acoustic / general, each in solve order, so
+// the tiles of the solves still running are a prefix whose length,
+// table_len[live], the device computed in the prologue); each XCD takes a
+// contiguous band of every round.  Every solve keeps its own grid, tables,
+// step count and source coefficients; the per-cell arithmetic is the
+// single-solve tile code.
+template <int BY, bool AC>
 __global__ void __launch_bounds__(kSeg * BY)
-    k_velocity_batched(const StepArgs *__restrict__ desc, const BatchTile *__restrict__ tiles,
-                       int n_tiles, const float2 *__restrict__ coef, int max_steps, int n) {
-  int staged = -1;
-  const int b = xcd_band(blockIdx.x, gridDim.x);
-  for (int t = b; t < n_tiles; t += gridDim.x) {
-    const BatchTile tl = tiles[t];
+    k_velocity_batched(BatchWalk W, const float2 *__restrict__ coef, int max_steps, int n) {
+  const int len = ((const ScalarI32 *)W.table_len)[W.live];
+  int staged = -1, t, stride;
+  if ((int)gridDim.x >= len) {  // one block per tile
+    if ((int)blockIdx.x >= len) return;
+    t = xcd_band(blockIdx.x, len);
+    stride = len;
+  } else {                      // persistent blocks
+    t = xcd_band(blockIdx.x, gridDim.x);
+    stride = gridDim.x;
+  }
+  for (; t < len; t += stride) {
+    // uniform reads through the scalar cache: the tile, then its solve's arguments
+    const BatchTile tl = scalar_copy(W.tiles + ((const ScalarI32 *)W.table)[t]);
+    const StepArgs A = scalar_copy(W.desc + tl.solve);
     if (tl.solve != staged) {
       __syncthreads();
-      stage_lut(s_lut, desc[tl.solve].lut, desc[tl.solve].n_mat);
+      stage_lut(s_lut, A.lut, A.n_mat);
       __syncthreads();
       staged = tl.solve;
     }
     const float2 cs = coef[(long long)tl.solve * max_steps + n];
-    if (tl.kind)
-      velocity_ac_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x,
-                       cs.y);
+    if (AC)
+      velocity_ac_tile(A, s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x, cs.y);
     else
-      velocity_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x, cs.y);
+      velocity_tile(A, s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, cs.x, cs.y);
   }
 }
 
-template <int BY>
+template <int BY, bool AC>
 __global__ void __launch_bounds__(kSeg * BY)
-    k_stress_batched(const StepArgs *__restrict__ desc, const BatchTile *__restrict__ tiles,
-                     int n_tiles, const int *__restrict__ cap, int n) {
-  int staged = -1;
-  const int b = xcd_band(blockIdx.x, gridDim.x);
-  for (int t = b; t < n_tiles; t += gridDim.x) {
-    const BatchTile tl = tiles[t];
+    k_stress_batched(BatchWalk W, const int *__restrict__ cap, int n) {
+  const int len = ((const ScalarI32 *)W.table_len)[W.live];
+  int staged = -1, t, stride;
+  if ((int)gridDim.x >= len) {  // one block per tile
+    if ((int)blockIdx.x >= len) return;
+    t = xcd_band(blockIdx.x, len);
+    stride = len;
+  } else {                      // persistent blocks
+    t = xcd_band(blockIdx.x, gridDim.x);
+    stride = gridDim.x;
+  }
+  for (; t < len; t += stride) {
+    // uniform reads through the scalar cache: the tile, then its solve's arguments
+    const BatchTile tl = scalar_copy(W.tiles + ((const ScalarI32 *)W.table)[t]);
+    const StepArgs A = scalar_copy(W.desc + tl.solve);
     if (tl.solve != staged) {
       __syncthreads();
-      stage_lut(s_lut, desc[tl.solve].lut, desc[tl.solve].n_mat);
+      stage_lut(s_lut, A.lut, A.n_mat);
       __syncthreads();
       staged = tl.solve;
     }
     const int capture = (n + 1 >= cap[tl.solve]) ? 1 : 0;
-    if (tl.kind)
-      stress_ac_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, capture);
+    if (AC)
+      stress_ac_tile(A, s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, capture);
     else
-      stress_tile(desc[tl.solve], s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, capture);
+      stress_tile(A, s_lut, tl.bx, tl.by * BY + wave_row(), tl.k0, tl.k1, capture);
+  }
+}
+
+// Stable split of the batch tile table by kind, and the live lengths of both
+// tables: len[kind][q] = tiles of that kind among the first q solves
+// (solve_end[q - 1] = end of solve q - 1's tiles in the table).  One block.
+__global__ void __launch_bounds__(kListThreads)
+    k_batch_split(const BatchTile *__restrict__ tiles, int n, const int *__restrict__ solve_end,
+                  int n_solves, int *__restrict__ table_ac, int *__restrict__ table_gen,
+                  int *__restrict__ scan, int *__restrict__ len_ac, int *__restrict__ len_gen) {
+  __shared__ int sc[kListThreads];
+  __shared__ int base;
+  const int t = threadIdx.x;
+  if (t == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n; c0 += kListThreads) {
+    const int id = c0 + t;
+    const int f = (id < n && tiles[id].kind) ? 1 : 0;
+    sc[t] = f;
+    __syncthreads();
+    for (int o = 1; o < kListThreads; o <<= 1) {
+      const int v = t >= o ? sc[t - o] : 0;
+      __syncthreads();
+      sc[t] += v;
+      __syncthreads();
+    }
+    const int incl = base + sc[t];
+    if (id < n) {
+      scan[id] = incl;
+      if (f) table_ac[incl - 1] = id;
+      else table_gen[id - incl] = id;
+    }
+    __syncthreads();
+    if (t == kListThreads - 1) base += sc[t];
+    __syncthreads();
+  }
+  for (int q = t; q <= n_solves; q += kListThreads) {
+    const int end = q == 0 ? 0 : solve_end[q - 1];
+    const int ac = end == 0 ? 0 : scan[end - 1];
+    len_ac[q] = ac;
+    len_gen[q] = end - ac;
   }
 }
 
@@ -707,6 +807,26 @@ __global__ void k_classify(const uint8_t *__restrict__ idx, uint8_t *__restrict_
           }
       }
     cls[r * kpad + k] = ok ? (uint8_t)(m + 1) : (uint8_t)0;
+  }
+}
+
+// Keep flags (see StepArgs::keep): 1 where a class-0 (elastic) segment of the
+// same x segment lies within rows j-2..j+1 of the same plane (it reads
+// sigma_yy here) or within planes k-2..k+1 of the same row (sigma_zz).
+__global__ void k_keep(const uint8_t *__restrict__ cls, uint8_t *__restrict__ keep, Grid g,
+                       int nseg, int kpad) {
+  const long long total = (long long)nseg * g.ny * g.nz;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(t % g.nz);
+    const long long r = t / g.nz;
+    const int sg = (int)(r % nseg), j = (int)(r / nseg);
+    bool need = false;
+    for (int jj = max(j - 2, 0); !need && jj <= min(j + 1, g.ny - 1); ++jj)
+      need = cls[((long long)jj * nseg + sg) * kpad + k] == 0;
+    for (int kk = max(k - 2, 0); !need && kk <= min(k + 1, g.nz - 1); ++kk)
+      need = cls[r * kpad + kk] == 0;
+    keep[r * kpad + k] = need ? 1 : 0;
   }
 }
 
@@ -867,9 +987,10 @@ hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_ma
   return hipGetLastError();
 }
 
-hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, const Grid &g, int nseg, int kpad,
-                           const float *lut, hipStream_t s) {
+hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, uint8_t *keep, const Grid &g, int nseg,
+                           int kpad, const float *lut, hipStream_t s) {
   hipLaunchKernelGGL(k_classify, dim3(4096), dim3(256), 0, s, idx, cls, g, nseg, kpad, lut);
+  hipLaunchKernelGGL(k_keep, dim3(4096), dim3(256), 0, s, cls, keep, g, nseg, kpad);
   return hipGetLastError();
 }
 
@@ -889,29 +1010,37 @@ hipError_t launch_fill(float *p, long long n, float v, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Batched step: the four persistent kernels over the live parts of the two
+// per-kind tables.  W[0] walks the acoustic table, W[1] the general one.
 template <int BY>
-static hipError_t batched_step(const StepArgs *desc, const BatchTile *tiles, int n_tiles,
-                               const float2 *coef, const int *cap, int max_steps, int n,
-                               int blocks, int max_mat, hipStream_t s) {
-  const dim3 grid(min(blocks, n_tiles)), block(kSeg, BY, 1);
-  hipLaunchKernelGGL(k_velocity_batched<BY>, grid, block, lut_bytes(max_mat), s, desc, tiles,
-                     n_tiles, coef, max_steps, n);
-  hipLaunchKernelGGL(k_stress_batched<BY>, grid, block, lut_bytes(max_mat), s, desc, tiles,
-                     n_tiles, cap, n);
+static hipError_t batched_step(const BatchWalk *W, const float2 *coef, const int *cap,
+                               int max_steps, int n, int blocks, int max_mat, hipStream_t s) {
+  const dim3 grid(blocks), block(kSeg, BY, 1);
+  const size_t lds = lut_bytes(max_mat);
+  hipLaunchKernelGGL((k_velocity_batched<BY, true>), grid, block, lds, s, W[0], coef, max_steps, n);
+  hipLaunchKernelGGL((k_velocity_batched<BY, false>), grid, block, lds, s, W[1], coef, max_steps, n);
+  hipLaunchKernelGGL((k_stress_batched<BY, true>), grid, block, lds, s, W[0], cap, n);
+  hipLaunchKernelGGL((k_stress_batched<BY, false>), grid, block, lds, s, W[1], cap, n);
   return hipGetLastError();
 }
 
-hipError_t launch_batched_step(int by, const StepArgs *desc, const BatchTile *tiles, int n_tiles,
-                               const float2 *coef, const int *cap, int max_steps, int n,
-                               int blocks, int max_mat, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
+hipError_t launch_batched_step(int by, const BatchWalk *W, const float2 *coef, const int *cap,
+                               int max_steps, int n, int blocks, int max_mat, hipStream_t s) {
   switch (by) {
-    case 1: return batched_step<1>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, max_mat, s);
-    case 2: return batched_step<2>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, max_mat, s);
-    case 4: return batched_step<4>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, max_mat, s);
-    case 8: return batched_step<8>(desc, tiles, n_tiles, coef, cap, max_steps, n, blocks, max_mat, s);
+    case 1: return batched_step<1>(W, coef, cap, max_steps, n, blocks, max_mat, s);
+    case 2: return batched_step<2>(W, coef, cap, max_steps, n, blocks, max_mat, s);
+    case 4: return batched_step<4>(W, coef, cap, max_steps, n, blocks, max_mat, s);
+    case 8: return batched_step<8>(W, coef, cap, max_steps, n, blocks, max_mat, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_batch_split(const BatchTile *tiles, int n, const int *solve_end, int n_solves,
+                              int *table_ac, int *table_gen, int *scan, int *len_ac, int *len_gen,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_split, dim3(1), dim3(kListThreads), 0, s, tiles, n, solve_end,
+                     n_solves, table_ac, table_gen, scan, len_ac, len_gen);
+  return hipGetLastError();
 }
 
 int argmax_partials() { return kRedBlocks; }
