@@ -74,6 +74,8 @@ def test_elements_match_oracle():
     (dict(materials=np.array([[1000.0, 1500.0, 0, 0, 0], [1900.0, 2800.0, 1500.0, 5000.0, 0]])),
      bb.EMATERIAL),
     (dict(materials=np.array([[0.0, 1500.0, 0, 0, 0]])), bb.EMATERIAL),
+    # padded arrays beyond 4 GiB: the step kernels use 32-bit byte offsets
+    (dict(nx=1100, ny=1100, nz=1100), bb.EINVAL),
 ])
 def test_plan_rejects(bad, code):
     kw = dict(nx=64, ny=64, nz=64, freq_hz=250e3, ppw=6.0, n_steps=100,
@@ -94,3 +96,13 @@ def test_workspace_layout_fits_every_workload():
         assert plan.workspace_bytes >= 33 * 4 * cells_padded + cells_padded
         assert plan.workspace_bytes < 1.2 * (33 * 4 + 1) * cells_padded + (1 << 20)
         assert plan.info["pitch"] % 32 == 0 and plan.info["pitch"] >= case.nx + 4
+
+
+def test_tile_shape_reported():
+    """Tiles are 64 x 4 cells x at most 8 planes, shorter marches on small grids
+    so that a launch still has thousands of tiles."""
+    for case, planes in ((synth.plate_case(), 1), (synth.skull200(build_map=False), 6),
+                         (synth.skull400(build_map=False), 8)):
+        info = bb.Plan.from_case(case).info
+        assert info["tile_rows"] == 4
+        assert info["tile_planes"] == planes, (case.name, info["tile_planes"])
