@@ -42,6 +42,7 @@ typedef struct {
   int32_t width;  /* channels of the hidden layers */
   int32_t layers; /* Fourier layers */
   int32_t mx, my, mz; /* kept modes per axis (mx <= n/2, 2my <= n, 2mz <= n) */
+  float loss_focus;   /* training loss weight: w = 1 + loss_focus * exp(target) (>= 0) */
 } bbsur_config;
 
 typedef struct bbsur_model bbsur_model;
@@ -62,7 +63,10 @@ int bbsur_forward(const bbsur_model *model, const float *params, const float *x,
 int bbsur_backward(const bbsur_model *model, const float *params, const float *x,
                    const float *dy, float *grad, int32_t batch, void *workspace,
                    uint64_t workspace_bytes, void *stream);
-/* One Adam step on the mean squared error to target ([batch][n^3]):
+/* One Adam step on the weighted mean squared error to target ([batch][n^3]),
+   mean over cells of w (y - target)^2 with w = 1 + loss_focus exp(target)
+   (targets are logs of normalised pressure, so the weight grows with the
+   pressure the target stands for; loss_focus = 0 is the plain MSE):
    forward, loss (written to loss_dev[0]), backward, update of params with
    moments m, v (n_params floats each, zero at step 1).  step counts from 1. */
 int bbsur_train_step(const bbsur_model *model, float *params, float *grad, float *m, float *v,

@@ -201,14 +201,15 @@ __global__ void k_sum_rows(const float *__restrict__ in, float *__restrict__ out
 constexpr int kLossThreads = 256;
 __global__ void __launch_bounds__(kLossThreads)
     k_loss(const float *__restrict__ y, const float *__restrict__ tgt, float *__restrict__ dy,
-           float *__restrict__ partial, long long n, float inv_count) {
+           float *__restrict__ partial, long long n, float inv_count, float focus) {
   __shared__ float sh[kLossThreads];
   float acc = 0.f;
   for (long long t = blockIdx.x * (long long)kLossThreads + threadIdx.x; t < n;
        t += (long long)gridDim.x * kLossThreads) {
+    const float w = focus > 0.f ? 1.f + focus * expf(tgt[t]) : 1.f;
     const float d = y[t] - tgt[t];
-    dy[t] = 2.f * d * inv_count;
-    acc += d * d;
+    dy[t] = 2.f * w * d * inv_count;
+    acc += w * d * d;
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -299,9 +300,10 @@ hipError_t launch_sum_rows(const float *in, float *out, int R, int M, hipStream_
 constexpr int kLossBlocks = 1024;
 int loss_partials() { return kLossBlocks; }
 hipError_t launch_loss(const float *y, const float *t, float *dy, float *partial, float *loss,
-                       long long n, hipStream_t s) {
+                       float focus, long long n, hipStream_t s) {
   const float inv = 1.f / (float)n;
-  hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(kLossThreads), 0, s, y, t, dy, partial, n, inv);
+  hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(kLossThreads), 0, s, y, t, dy, partial, n, inv,
+                     focus);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, partial, kLossBlocks, inv, loss);
   return hipGetLastError();
 }

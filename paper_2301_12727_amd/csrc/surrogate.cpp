@@ -42,7 +42,7 @@ hipError_t launch_mix_bwd(const float *U, const float *dV, const float *R, float
 hipError_t launch_sum_rows(const float *in, float *out, int R, int M, hipStream_t s);
 int loss_partials();
 hipError_t launch_loss(const float *y, const float *t, float *dy, float *partial, float *loss,
-                       long long n, hipStream_t s);
+                       float focus, long long n, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr_t,
                        float b1, float b2, float eps_t, hipStream_t s);
 hipError_t launch_features(const uint8_t *mat, const float2 *table, int n_table,
@@ -399,7 +399,8 @@ int bbsur_create(const bbsur_config *cfg, bbsur_model **out) {
   if (!cfg) return fail(BBFD_EINVAL, "null config");
   const bbsur_config &c = *cfg;
   if (c.n < 4 || c.n > 256 || c.cin < 1 || c.width < 1 || c.width > 256 || c.layers < 1 ||
-      c.mx < 1 || c.my < 1 || c.mz < 1 || 2 * c.mx > c.n || 2 * c.my > c.n || 2 * c.mz > c.n)
+      c.mx < 1 || c.my < 1 || c.mz < 1 || 2 * c.mx > c.n || 2 * c.my > c.n || 2 * c.mz > c.n ||
+      !(c.loss_focus >= 0.f))
     return fail(BBFD_EINVAL, "bad surrogate configuration");
   bbsur_model *m = new (std::nothrow) bbsur_model();
   if (!m) return fail(BBFD_EINVAL, "out of host memory");
@@ -496,7 +497,7 @@ int bbsur_train_step(const bbsur_model *m, float *params, float *grad, float *mo
   if (!rc) rc = forward(c, params, x);
   if (!rc)
     rc = hipchk(launch_loss(c.ws + c.o.y, target, c.ws + c.o.dy, c.ws + c.o.lossp, loss_dev,
-                            (long long)batch * m->P, c.s), "loss");
+                            m->c.loss_focus, (long long)batch * m->P, c.s), "loss");
   if (!rc) rc = backward(c, params, x, c.ws + c.o.dy, grad);
   if (!rc) {
     const double b1 = 0.9, b2 = 0.999, eps = 1e-8;

@@ -15,7 +15,8 @@ _SIG_DONE = False
 
 
 class Config(C.Structure):
-    _fields_ = [(n, C.c_int32) for n in ("n", "cin", "width", "layers", "mx", "my", "mz")]
+    _fields_ = [(n, C.c_int32) for n in ("n", "cin", "width", "layers", "mx", "my", "mz")] + [
+        ("loss_focus", C.c_float)]
 
 
 def _sigs():
@@ -69,9 +70,9 @@ class TrainState:
 class Surrogate:
     """3D Fourier neural operator (see include/bbsur.h)."""
 
-    def __init__(self, n=64, cin=4, width=32, layers=4, mx=8, my=8, mz=8):
+    def __init__(self, n=64, cin=4, width=32, layers=4, mx=8, my=8, mz=8, loss_focus=0.0):
         L = _sigs()
-        self.cfg = Config(n, cin, width, layers, mx, my, mz)
+        self.cfg = Config(n, cin, width, layers, mx, my, mz, loss_focus)
         self.h = C.c_void_p()
         _check(L.bbsur_create(C.byref(self.cfg), C.byref(self.h)))
         np_ = C.c_uint64(0)

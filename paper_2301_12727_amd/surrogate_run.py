@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--modes", type=int, default=8)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--focus", type=float, default=0.0,
+                    help="loss weight 1 + focus * P/P_free (0: plain MSE of the log map)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
@@ -231,7 +233,7 @@ def main():
     dev = generate(ev_seeds, args.n, keep_masks=True)
     ratio = float(np.mean(dtr.peak_post / dtr.free_post))
     model = sg.Surrogate(n=args.n, cin=4, width=args.width, layers=args.layers,
-                         mx=args.modes, my=args.modes, mz=args.modes)
+                         mx=args.modes, my=args.modes, mz=args.modes, loss_focus=args.focus)
     params, hist = train(model, dtr, args.seconds, batch=args.batch, lr=args.lr)
     res = evaluate(model, params, dev, ratio)
     gate = Gate(dtr.stats)
@@ -282,6 +284,7 @@ def main():
     del yb
     out = {"config": {"n": args.n, "width": args.width, "layers": args.layers,
                       "modes": args.modes, "params": model.n_params, "train": args.train,
+                      "loss_focus": args.focus,
                       "eval": args.eval, "batch": args.batch, "seconds": args.seconds},
            "generation_s": round(t_gen, 1), "training": hist, "eval": res,
            "train_mean_ratio": ratio, "gate_in_distribution_frac": in_dist,

@@ -110,3 +110,26 @@ def test_training_reduces_loss_on_a_fixed_batch():
     say(f"[surrogate] loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert losses[-1] < 0.5 * losses[0]
     del rng
+
+
+def test_weighted_loss_value_and_step():
+    """Loss of a training step equals mean(w (y - t)^2) with w = 1 + f exp(t),
+    y the forward output at the step's starting parameters; training with the
+    weight still reduces the loss."""
+    p, x = _setup(2, 4)
+    target = np.tanh(nn_ref.forward(nn_ref.init_params(CFG, 9), x.astype(np.float64), CFG))
+    focus = 3.0
+    model = sg.Surrogate(**CFG.__dict__, loss_focus=focus)
+    xs = torch.from_numpy(x).cuda()
+    ts = torch.from_numpy(target.astype(np.float32)).cuda()
+    pt = torch.from_numpy(p).cuda()
+    y = model.forward(pt, xs).cpu().numpy().astype(np.float64)
+    t64 = target.astype(np.float32).astype(np.float64)
+    w = 1.0 + focus * np.exp(t64)
+    expect = float(np.mean(w * (y.reshape(t64.shape) - t64) ** 2))
+    st = model.train_state(pt.clone())
+    got = model.train_step(st, xs, ts, lr=3e-3)
+    say(f"[surrogate] weighted loss {got:.6e} vs {expect:.6e}")
+    assert abs(got - expect) <= 1e-4 * expect
+    losses = [model.train_step(st, xs, ts, lr=3e-3) for _ in range(60)]
+    assert losses[-1] < 0.5 * got
