@@ -212,14 +212,14 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--eval", type=int, default=200)
-    ap.add_argument("--seconds", type=float, default=420.0)
+    ap.add_argument("--seconds", type=float, default=600.0)
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--width", type=int, default=32)
     ap.add_argument("--layers", type=int, default=4)
     ap.add_argument("--modes", type=int, default=8)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--focus", type=float, default=0.0,
+    ap.add_argument("--focus", type=float, default=10.0,
                     help="loss weight 1 + focus * P/P_free (0: plain MSE of the log map)")
     args = ap.parse_args()
     import torch
