@@ -1,21 +1,24 @@
 // Viscoelastic FDTD step kernels for gfx950 (BabelBrain Section 2.3, Eq. 1).
 //
-// One time step is two launches:
-//   k_velocity : v^{n-1/2} -> v^{n+1/2} (Eq. 1 rows 1-3) and the source force
-//                on the v_z faces of plane ks (Section 2.3)
-//   k_stress   : sigma^n -> sigma^{n+1}, Zener memory variables, peak |p|
-//                capture (Eq. 1 rows 4-9, Section 3.2)
-// Both are HBM-bandwidth-bound stencils.  A tile is a 64 x 4 block of x-y
-// columns marching over a chunk of z; x is the fastest (coalesced) axis and
-// each wave owns one 64-cell row segment, so the segment class (acoustic or
-// elastic branch) is wave-uniform.  Per block the material table is staged
-// in LDS, so the material gathers of a cell are LDS reads rather than a
-// second dependent trip to the cache hierarchy, and the class bytes of a
+// One time step is four launches over the tiles of a solve (64 x 4 x-y
+// columns marching over up to 8 planes of z), split once per solve into
+// acoustic tiles (every row segment a single lossless fluid throughout the
+// stencil's reach) and general tiles:
+//   k_velocity_ac, k_velocity : v^{n-1/2} -> v^{n+1/2} (Eq. 1 rows 1-3) and
+//                the source force on the v_z faces of plane ks (Section 2.3)
+//   k_stress_ac, k_stress     : sigma^n -> sigma^{n+1}, Zener memory
+//                variables, peak |p| capture (Eq. 1 rows 4-9, Section 3.2)
+// All are HBM-bandwidth-bound stencils.  x is the fastest (coalesced) axis
+// and each wave owns one 64-cell row segment, so the segment class (acoustic
+// or elastic branch) is wave-uniform.  Per block the material table is
+// staged in LDS, so the material gathers of a cell are LDS reads rather than
+// a second dependent trip to the cache hierarchy, and the class bytes of a
 // segment's z column are read four at a time through the scalar cache, one
 // group ahead.  Tiles are assigned so that each XCD works on a contiguous
 // band of them, keeping the halo rows of neighbouring tiles in one L2.  The
 // absorbing layer (CPML) is applied per cell behind a slab test that is
-// uniform across most waves.
+// uniform across most waves.  Batched sweeps run the same tile code from
+// per-kind tables that span many solves.
 #include "bbfd_dev.h"
 
 namespace bbfd {
