@@ -241,3 +241,52 @@ def test_skull200_full_size_against_oracle_samples():
     plan.source_rayleigh(case.transducer, src, ws)
     torch.cuda.synchronize()
     assert rel_err_complex(src.cpu().numpy(), ref_src) <= TOL_SRC
+
+
+def mixed_tile_case(n_steps=90):
+    """90x36x60 water grid with a lossy solid block, a second lossless fluid
+    and a lossy fluid: acoustic tiles (two fluid classes), general tiles, and
+    acoustic segments next to elastic ones (which keep all normal stresses)."""
+    nx, ny, nz, pml, f = 90, 36, 60, 6, 500e3
+    mats = synth._rows(synth.table1(f)["water"],
+                       (1850.0, 2700.0, 1300.0, 80.0, 200.0),     # lossy solid
+                       (1100.0, 1700.0, 0.0, 0.0, 0.0),           # lossless fluid
+                       (1050.0, 1560.0, 0.0, 30.0, 0.0))          # lossy fluid
+    mat = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mat[25:35, 10:26, 40:70] = 1
+    mat[40:52, :, 0:40] = 2
+    mat[12:20, 20:30, 70:85] = 3
+    case = synth.Case("mixedtiles", nx, ny, nz, pml, f, 6.0, n_steps, mats, mat, None)
+    dx, zs = case.dx, case.source_plane_z()
+    radius = 0.3 * min(nx, ny) * dx
+    focal = 2.4 * radius
+    fz = synth.bowl_focus_for_standoff(zs, radius, focal, (0.0, 0.0, 1.0), 2e-3)
+    case.transducer = synth.Transducer(1, radius, focal, (nx // 2 * dx, ny // 2 * dx, fz - focal),
+                                       (0.0, 0.0, 1.0))
+    return case
+
+
+def test_acoustic_and_general_tiles_side_by_side():
+    case = mixed_tile_case()
+    P, ref = compare_case(case)
+    # the case does exercise both tile kinds and both fluid classes
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace()
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device="cuda")
+    plan.source_rayleigh(case.transducer, src, ws)
+    mat = torch.from_numpy(case.mat).cuda()
+    peak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    plan.solve(mat, src, peak, ws)
+    plan.status(ws)
+    cls = plan.segment_classes(ws)
+    R, K = plan.info["tile_rows"], plan.info["tile_planes"]
+    nseg = cls.shape[2]
+    nby, nzc = -(-case.ny // R), -(-case.nz // K)
+    pad = np.ones((nzc * K, nby * R, nseg), dtype=bool)
+    pad[:case.nz, :case.ny] = cls != 0
+    kinds = pad.reshape(nzc, K, nby, R, nseg).all(axis=(1, 3))
+    say(f"[parity] classes {sorted(set(cls.ravel().tolist()))}, acoustic tiles "
+        f"{int(kinds.sum())} of {kinds.size}")
+    assert {0, 1, 3} <= set(cls.ravel().tolist())
+    assert 0 < kinds.sum() < kinds.size
+    assert np.array_equal(peak.cpu().numpy(), P)
