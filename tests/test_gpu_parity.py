@@ -254,7 +254,7 @@ def mixed_tile_case(n_steps=90):
                        (1050.0, 1560.0, 0.0, 30.0, 0.0))          # lossy fluid
     mat = np.zeros((nz, ny, nx), dtype=np.uint8)
     mat[25:35, 10:26, 40:70] = 1
-    mat[40:52, :, 0:40] = 2
+    mat[40:52, :, 0:67] = 2                                     # spans x segment 0 and its reach
     mat[12:20, 20:30, 70:85] = 3
     case = synth.Case("mixedtiles", nx, ny, nz, pml, f, 6.0, n_steps, mats, mat, None)
     dx, zs = case.dx, case.source_plane_z()
