@@ -189,11 +189,23 @@ __global__ void k_mix_bwd_weight(const float *__restrict__ U, const float *__res
 }
 
 // out[m] = sum_r in[r * M + m]  (fixed order: deterministic)
-__global__ void k_sum_rows(const float *__restrict__ in, float *__restrict__ out, int R, int M) {
-  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < M; m += gridDim.x * blockDim.x) {
-    float acc = 0.f;
-    for (int r = 0; r < R; ++r) acc += in[(long long)r * M + m];
-    out[m] = acc;
+// out[m] = sum over r of in[r][m].  A block owns 64 consecutive m; its 16
+// thread rows take every 16th r, and the 16 partial sums are added in a
+// fixed order, so the result does not depend on scheduling.
+constexpr int kSumCols = 64, kSumRows = 16;
+__global__ void __launch_bounds__(kSumCols * kSumRows)
+    k_sum_rows(const float *__restrict__ in, float *__restrict__ out, int R, int M) {
+  __shared__ float part[kSumRows][kSumCols];
+  const int m = blockIdx.x * kSumCols + threadIdx.x;
+  float acc = 0.f;
+  if (m < M)
+    for (int r = threadIdx.y; r < R; r += kSumRows) acc += in[(long long)r * M + m];
+  part[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.y == 0 && m < M) {
+    float s = 0.f;
+    for (int q = 0; q < kSumRows; ++q) s += part[q][threadIdx.x];
+    out[m] = s;
   }
 }
 
@@ -294,7 +306,8 @@ hipError_t launch_mix_bwd(const float *U, const float *dV, const float *R, float
   return hipGetLastError();
 }
 hipError_t launch_sum_rows(const float *in, float *out, int R, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_rows, dim3(grid_for(M)), dim3(256), 0, s, in, out, R, M);
+  hipLaunchKernelGGL(k_sum_rows, dim3((M + kSumCols - 1) / kSumCols), dim3(kSumCols, kSumRows), 0, s,
+                     in, out, R, M);
   return hipGetLastError();
 }
 constexpr int kLossBlocks = 1024;

@@ -85,7 +85,7 @@ namespace {
 struct Layout {
   size_t mats, ones, h, z, U, T1, T2, V, I1, I2, y, dy, lossp, loss, dh, dh2, dz, dV, dU, part,
       bpart, total;
-  long long Kc, S;  // split-K chunk (n^2) and chunk count (n)
+  long long Kc, S;  // split-K chunk and chunk count (Kc * S = n^3)
 };
 
 Layout layout(const bbsur_model *m, int B) {
@@ -97,8 +97,10 @@ Layout layout(const bbsur_model *m, int B) {
     return r;
   };
   const long long BW = (long long)B * m->W;
-  o.Kc = m->n2;
-  o.S = m->n;
+  // weight gradients contract over all n^3 cells: split them into chunks of
+  // n^2 / 4 cells (n^2 for small n) so a gradient launch has 4n blocks
+  o.Kc = (m->n2 % 4 == 0 && m->n2 >= 1024) ? m->n2 / 4 : m->n2;
+  o.S = m->P / o.Kc;
   o.mats = take(m->mats.size());
   o.ones = take(o.Kc);
   o.h = take((size_t)(m->L + 1) * BW * m->P);
