@@ -98,8 +98,8 @@ Layout layout(const bbsur_model *m, int B) {
   };
   const long long BW = (long long)B * m->W;
   // weight gradients contract over all n^3 cells: split them into chunks of
-  // n^2 / 4 cells (n^2 for small n) so a gradient launch has 4n blocks
-  o.Kc = (m->n2 % 4 == 0 && m->n2 >= 1024) ? m->n2 / 4 : m->n2;
+  // n^2 / 16 cells (n^2 for small n) so a gradient launch has 16n blocks
+  o.Kc = (m->n2 % 16 == 0 && m->n2 >= 4096) ? m->n2 / 16 : m->n2;
   o.S = m->P / o.Kc;
   o.mats = take(m->mats.size());
   o.ones = take(o.Kc);
