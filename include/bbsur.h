@@ -2,7 +2,7 @@
  * bbsur -- learned surrogate of the transcranial FDTD solve: a 3D Fourier
  * neural operator mapping per-cell speed, density and incident-field phase of
  * an n^3 domain to the log peak-pressure map, trained on FDTD solves of libbbfd
- * and falling back to them (the FDTD solve stays the judge of its error).
+ * and falling back to them (the FDTD solve stays the reference for its error).
  *
  * Every contraction (lifting, pointwise layers, the truncated Fourier
  * transforms written as matrix products, projection, and all their gradients)
