@@ -47,16 +47,43 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-KERNELS = ("velocity_ac", "velocity", "stress_ac", "stress")
+KERNELS = ("velocity_ac", "velocity", "stress_ac", "stress", "step_deep")
+REACH = 3   # cells around a deep tile that its fused step reads
+
+
+def tile_kinds(case, info, classes):
+    """Kind of every tile as the library assigns it: 0 general, 1 acoustic,
+    2 deep (acoustic, inside the grid and outside the layer with REACH cells
+    around it, one fluid class over the tile, its reach and the neighbouring
+    x segments).  Returns kinds [nz-chunks][row blocks][segments]."""
+    import numpy as np
+    nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
+    R, K = int(info["tile_rows"]), int(info["tile_planes"])
+    seg = classes != 0
+    nseg = seg.shape[2]
+    nby, nzc = -(-ny // R), -(-nz // K)
+    pad = np.ones((nzc * K, nby * R, nseg), dtype=bool)
+    pad[:nz, :ny] = seg
+    kind = pad.reshape(nzc, K, nby, R, nseg).all(axis=(1, 3)).astype(np.int8)
+    for kc, by, bx in zip(*np.nonzero(kind)):
+        i0, j0, k0 = 64 * bx, R * by, K * kc
+        k1 = min(k0 + K, nz)
+        if not (i0 - REACH >= L and i0 + 63 + REACH < nx - L and j0 - REACH >= L
+                and j0 + R - 1 + REACH < ny - L and k0 - REACH >= L and k1 - 1 + REACH < nz - L):
+            continue
+        blk = classes[k0 - REACH:k1 + REACH, j0 - REACH:j0 + R + REACH, bx - 1:bx + 2]
+        if (blk == classes[k0, j0, bx]).all():
+            kind[kc, by, bx] = 2
+    return kind
 
 
 def algorithmic_bytes(case, info, classes) -> dict:
     """Bytes each step kernel must move per launch at perfect on-chip reuse
     (FP32 state, 1-byte index), averaged over the time loop.  ``classes`` is
     the library's row-segment class map: cells of class > 0 are acoustic (one
-    lossless fluid throughout the stencil's reach).  A tile (64 x tile_rows x
-    tile_planes cells) all of whose segments are acoustic runs the *_ac
-    kernels, every other tile the general ones.
+    lossless fluid throughout the stencil's reach).  Tiles (64 x tile_rows x
+    tile_planes cells) run by kind (see tile_kinds): deep tiles the fused step,
+    other acoustic tiles the *_ac kernels, the rest the general ones.
       velocity, elastic cell: read 6 stresses + 3 velocities + index, write 3
                 velocities = 49 B; acoustic cell: read 1 normal stress + 3
                 velocities, write 3 velocities = 28 B.  Per absorbing-layer axis
@@ -67,17 +94,15 @@ def algorithmic_bytes(case, info, classes) -> dict:
                 1 normal stress, write 3 normal stresses = 28 B, or only sigma_xx
                 (20 B) in an acoustic tile where no elastic segment within 2 rows
                 or planes reads sigma_yy / sigma_zz (keep flag).  Layer memories
-                as above.  Capture steps add 8 B/cell (peak read + write)."""
+                as above.  Capture steps add 8 B/cell (peak read + write).
+      step_deep, fused velocity + stress of a deep tile: read sigma_xx and 3
+                velocities, write them = 32 B per cell, + capture as above."""
     import numpy as np
     nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
     R, K = int(info["tile_rows"]), int(info["tile_planes"])
-    seg = classes != 0                                     # [nz][ny][nseg]
-    nseg = seg.shape[2]
-    nby, nzc = -(-ny // R), -(-nz // K)
-    pad = np.ones((nzc * K, nby * R, nseg), dtype=bool)
-    pad[:nz, :ny] = seg
-    kind = pad.reshape(nzc, K, nby, R, nseg).all(axis=(1, 3))      # acoustic tiles
-    tile_ac = np.repeat(np.repeat(np.repeat(kind, K, 0)[:nz], R, 1)[:, :ny], 64, 2)[:, :, :nx]
+    seg = (classes != 0)
+    kind = tile_kinds(case, info, classes)
+    cell_kind = np.repeat(np.repeat(np.repeat(kind, K, 0)[:nz], R, 1)[:, :ny], 64, 2)[:, :, :nx]
     fluid = np.repeat(seg, 64, axis=2)[:, :, :nx]
     # keep flags: an acoustic segment within 2 rows or 2 planes of an elastic
     # (class 0) segment of the same x segment stores sigma_yy and sigma_zz too
@@ -100,12 +125,12 @@ def algorithmic_bytes(case, info, classes) -> dict:
         axes_in_layer[tuple(sl)] += 1
     cap = (case.n_steps - info["capture_start"]) / case.n_steps
     out = {}
-    for name, mask in (("ac", tile_ac), ("gen", ~tile_ac)):
+    for name, mask in (("ac", cell_kind == 1), ("gen", cell_kind == 0)):
         fl = fluid & mask
-        el = ~fluid & mask
-        nf, ne = int(fl.sum()), int(el.sum())
+        el_c = ~fluid & mask
+        nf, ne = int(fl.sum()), int(el_c.sum())
         lf = int(axes_in_layer[fl].sum())
-        le = int(axes_in_layer[el].sum())
+        le = int(axes_in_layer[el_c].sum())
         src_cols = int(mask[info["source_k"]].sum())
         cls_bytes = int(mask.sum()) / 64
         suffix = "_ac" if name == "ac" else ""
@@ -114,9 +139,12 @@ def algorithmic_bytes(case, info, classes) -> dict:
         nk = int((fl & keep).sum()) if name == "ac" else nf
         out["stress" + suffix] = (20 * nf + 8 * nk + 109 * ne + 8 * lf + 24 * le
                                   + 8 * (nf + ne) * cap + cls_bytes * (2 if name == "ac" else 1))
+    nd = int((cell_kind == 2).sum())
+    out["step_deep"] = 32 * nd + 8 * nd * cap + nd / 64
     out["per_cell_update"] = sum(out[k] for k in KERNELS) / case.cells
     out["acoustic_fraction"] = float(fluid.mean())
-    out["acoustic_tile_fraction"] = float(tile_ac.mean())
+    out["acoustic_tile_fraction"] = float((cell_kind >= 1).mean())
+    out["deep_tile_fraction"] = nd / case.cells
     return out
 
 
@@ -304,7 +332,8 @@ def main():
                                        / (sum(avg.values()) * 1e-3) / 1e9, 1),
             "bytes_per_cell_update": round(ab["per_cell_update"], 2),
             "acoustic_cell_fraction": round(ab["acoustic_fraction"], 4),
-            "acoustic_tile_cell_fraction": round(ab["acoustic_tile_fraction"], 4)}
+            "acoustic_tile_cell_fraction": round(ab["acoustic_tile_fraction"], 4),
+            "deep_tile_cell_fraction": round(ab["deep_tile_fraction"], 4)}
 
     out = {
         "metric": "Gcell-updates/s",

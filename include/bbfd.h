@@ -145,13 +145,16 @@ int bbfd_solve_direct(const bbfd_plan *plan, const uint8_t *mat, const float *sr
 
 /* Profiling variant of bbfd_solve_direct: records a HIP event before and after
    every kernel of the time loop on stream, waits for the solve, and writes the
-   summed kernel times in milliseconds to ms_out[0..3]: the velocity update
+   summed kernel times in milliseconds to ms_out[0..4]: the velocity update
    (Eq. 1 rows 1-3) of the acoustic tiles [0] and of the general tiles [1],
    the stress/memory update (rows 4-9) of the acoustic tiles [2] and of the
-   general tiles [3].  A tile (64 x tile_rows x tile_planes cells, see
-   bbfd_plan_info) is acoustic when every one of its row segments is of a
-   lossless-fluid class (bbfd_segment_classes) on every plane; it then runs
-   kernels specialised to that case.  Results are identical to bbfd_solve. */
+   general tiles [3], and the fused velocity + stress step of the deep tiles
+   [4].  A tile (64 x tile_rows x tile_planes cells, see bbfd_plan_info) is
+   acoustic when every one of its row segments is of a lossless-fluid class
+   (bbfd_segment_classes) on every plane, and deep when moreover it lies, with
+   3 cells around it, inside the grid and outside the absorbing layer and all
+   of those cells hold one fluid; such tiles run kernels specialised to those
+   cases.  Results are identical to bbfd_solve. */
 int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
                         float *peak, void *workspace, uint64_t workspace_bytes, void *stream,
                         double *ms_out);

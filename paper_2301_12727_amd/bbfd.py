@@ -205,10 +205,10 @@ class Plan:
 
     def solve_profiled(self, mat, src, peak, ws, stream=None):
         """Direct-launch solve with per-kernel HIP events on the launch stream;
-        returns the summed milliseconds of the four step kernels over the time
+        returns the summed milliseconds of the five step kernels over the time
         loop: (acoustic velocity, general velocity, acoustic stress, general
-        stress)."""
-        out = np.zeros(4, dtype=np.float64)
+        stress, fused step of the deep tiles)."""
+        out = np.zeros(5, dtype=np.float64)
         _check(lib().bbfd_solve_profiled(self.h, C.c_void_p(mat.data_ptr()),
                                          C.c_void_p(src.data_ptr()), C.c_void_p(peak.data_ptr()),
                                          C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),

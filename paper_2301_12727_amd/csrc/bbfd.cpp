@@ -27,6 +27,8 @@ hipError_t launch_stress(const StepArgs &a, const int *const *lists, const int *
                          hipStream_t s);
 hipError_t launch_tile_lists(const StepArgs &a, uint8_t *kind, int *const *lists, int *counts,
                              hipStream_t s);
+hipError_t launch_deep(const StepArgs &a, const int *const *lists, const int *counts,
+                       hipStream_t s);
 hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tiles, int by,
                               hipStream_t s);
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
@@ -110,7 +112,7 @@ struct bbfd_plan {
   int nseg = 1;
   int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
-         off_cls = 0, off_keep = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
+         off_cls = 0, off_keep = 0, off_alt = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
          ws_bytes = 0;
   int n_tiles = 0;
   std::mutex mu;
@@ -281,10 +283,11 @@ void layout(bbfd_plan *pl) {
   pl->off_keep = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->n_tiles = pl->nseg * (int)((p.ny + kRows - 1) / kRows) * ((p.nz + pl->kchunk - 1) / pl->kchunk);
   pl->off_kind = o; o += round_up((size_t)pl->n_tiles, 256);
-  pl->off_lists = o; o += round_up(2 * (size_t)pl->n_tiles * sizeof(int), 256);
+  pl->off_lists = o; o += round_up(3 * (size_t)pl->n_tiles * sizeof(int), 256);
   pl->off_counts = o; o += 256;
   pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
   pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
+  pl->off_alt = o; o += (size_t)kNOut * g.stride * sizeof(float);  // second buffers of v, sigma_ii
   pl->ws_bytes = o;
 }
 
@@ -315,6 +318,7 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
     a.f[f] = (float *)(ws + pl->off_state) + (size_t)f * pl->g.stride;
   for (int f = 0; f < kNPsi; ++f)
     a.psi[f] = (float *)(ws + pl->off_psi) + (size_t)f * pl->g.stride;
+  for (int f = 0; f < kNOut; ++f) a.fo[f] = a.f[f];  // in place unless the caller pairs buffers
   a.src = (const float2 *)src;
   a.peak = peak;
   a.relax_a = pl->relax_a;
@@ -362,7 +366,7 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
   if ((e = launch_fill((float *)(ws + pl->off_status), 256 / sizeof(float), 0.f, s)) != hipSuccess)
     return hip_fail(e, "status clear");
   if ((e = launch_fill((float *)(ws + pl->off_state),
-                       (long long)(kNState + kNPsi) * pl->g.stride, 0.f, s)) != hipSuccess)
+                       (long long)(kNState + kNPsi + kNOut) * pl->g.stride, 0.f, s)) != hipSuccess)
     return hip_fail(e, "state clear");
   const long long cells = (long long)p.nx * p.ny * p.nz;
   if ((e = launch_fill(peak, cells, 0.f, s)) != hipSuccess) return hip_fail(e, "peak clear");
@@ -375,7 +379,8 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
                            (const float *)(ws + pl->off_lut), s)) != hipSuccess)
     return hip_fail(e, "segment classes");
   StepArgs a = step_args(pl, mat, nullptr, peak, ws);
-  int *lists[2] = {(int *)(ws + pl->off_lists), (int *)(ws + pl->off_lists) + pl->n_tiles};
+  int *lists[3] = {(int *)(ws + pl->off_lists), (int *)(ws + pl->off_lists) + pl->n_tiles,
+                   (int *)(ws + pl->off_lists) + 2 * (size_t)pl->n_tiles};
   if ((e = launch_tile_lists(a, (uint8_t *)(ws + pl->off_kind), lists, (int *)(ws + pl->off_counts),
                              s)) != hipSuccess)
     return hip_fail(e, "tile lists");
@@ -392,9 +397,10 @@ int enqueue_epilogue(const bbfd_plan *pl, float *peak, char *ws, hipStream_t s) 
 }
 
 // Enqueue one whole solve on s (no synchronisation).  With ev != NULL (direct
-// launches only), ev[4n + q] / ev[4n + q + 1] bracket kernel q of step n
-// (q: 0 acoustic velocity, 1 general velocity, 2 acoustic stress, 3 general
-// stress), ev[4 n_steps] closes the last one.
+// launches only), ev[2 (5n + q)] / ev[2 (5n + q) + 1] bracket kernel q of step
+// n (q: 0 acoustic velocity, 1 general velocity, 2 acoustic stress, 3 general
+// stress, 4 fused step of the deep tiles).
+constexpr int kStepKernels = 5;
 int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
                   char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
   const bbfd_problem &p = pl->prob;
@@ -402,20 +408,47 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
   if (rc) return rc;
   hipError_t e;
   StepArgs a = step_args(pl, mat, src, peak, ws);
-  const int *lists[2] = {(const int *)(ws + pl->off_lists),
-                         (const int *)(ws + pl->off_lists) + pl->n_tiles};
+  const int *lists[3] = {(const int *)(ws + pl->off_lists),
+                         (const int *)(ws + pl->off_lists) + pl->n_tiles,
+                         (const int *)(ws + pl->off_lists) + 2 * (size_t)pl->n_tiles};
   const int *counts = (const int *)(ws + pl->off_counts);
+  // v and the normal stresses alternate between two buffers: the velocity
+  // update reads cur and writes nxt; the stress update reads the new velocity
+  // (nxt) and the current stresses (cur) and writes the stresses to nxt; the
+  // fused step of the deep tiles reads cur and writes nxt.
+  float *cur[kNOut], *nxt[kNOut];
+  for (int f = 0; f < kNOut; ++f) {
+    cur[f] = a.f[f];
+    nxt[f] = (float *)(ws + pl->off_alt) + (size_t)f * pl->g.stride;
+  }
   for (int n = 0; n < p.n_steps; ++n) {
     a.src_c = pl->src_c[n];
     a.src_s = pl->src_s[n];
     a.capture = (n + 1 >= pl->cap) ? 1 : 0;
-    for (int q = 0; q < 4; ++q) {
-      if (ev) (void)hipEventRecord(ev[4 * n + q], s);
-      e = q < 2 ? launch_velocity(a, lists, counts, q, s) : launch_stress(a, lists, counts, q - 2, s);
-      if (e != hipSuccess) return hip_fail(e, q < 2 ? "velocity launch" : "stress launch");
+    StepArgs av = a, as = a, ad = a;
+    for (int f = 0; f < kNOut; ++f) {
+      const bool vel = f <= VZ;
+      av.f[f] = cur[f];
+      av.fo[f] = vel ? nxt[f] : cur[f];
+      as.f[f] = vel ? nxt[f] : cur[f];
+      as.fo[f] = nxt[f];
+      ad.f[f] = cur[f];
+      ad.fo[f] = nxt[f];
     }
+    // order: both velocity kernels and the fused step (all read only cur),
+    // then the stress kernels (they read the new velocity of every tile)
+    static const int order[kStepKernels] = {0, 1, 4, 2, 3};
+    for (int qi = 0; qi < kStepKernels; ++qi) {
+      const int q = order[qi];
+      if (ev) (void)hipEventRecord(ev[2 * (kStepKernels * n + q)], s);
+      if (q < 2) e = launch_velocity(av, lists, counts, q, s);
+      else if (q < 4) e = launch_stress(as, lists, counts, q - 2, s);
+      else e = launch_deep(ad, lists, counts, s);
+      if (e != hipSuccess) return hip_fail(e, "step launch");
+      if (ev) (void)hipEventRecord(ev[2 * (kStepKernels * n + q) + 1], s);
+    }
+    for (int f = 0; f < kNOut; ++f) std::swap(cur[f], nxt[f]);
   }
-  if (ev) (void)hipEventRecord(ev[4 * p.n_steps], s);
   return enqueue_epilogue(pl, peak, ws, s);
 }
 
@@ -636,25 +669,25 @@ int bbfd_solve_profiled(const bbfd_plan *cpl, const uint8_t *mat, const float *s
     if ((rc = ensure_pinned(pl))) return rc;
   }
   const int n = pl->prob.n_steps;
-  std::vector<hipEvent_t> ev(4 * (size_t)n + 1, nullptr);
+  std::vector<hipEvent_t> ev(2 * kStepKernels * (size_t)n, nullptr);
   hipError_t e = hipSuccess;
   for (auto &x : ev)
     if ((e = hipEventCreate(&x)) != hipSuccess) break;
   if (e == hipSuccess) {
     hipStream_t s = (hipStream_t)stream;
     rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, s, ev.data());
-    if (rc == BBFD_OK && (e = hipEventSynchronize(ev.back())) != hipSuccess)
+    if (rc == BBFD_OK && (e = hipStreamSynchronize(s)) != hipSuccess)
       rc = hip_fail(e, "profiled solve sync");
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; rc == BBFD_OK && k < 4 * n; ++k) {
+    double t[kStepKernels] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; rc == BBFD_OK && k < kStepKernels * n; ++k) {
       float a = 0.f;
-      if (hipEventElapsedTime(&a, ev[k], ev[k + 1]) != hipSuccess) {
+      if (hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]) != hipSuccess) {
         rc = fail(BBFD_EHIP, "event timing");
         break;
       }
-      t[k % 4] += a;
+      t[k % kStepKernels] += a;
     }
-    for (int q = 0; q < 4; ++q) ms_out[q] = t[q];
+    for (int q = 0; q < kStepKernels; ++q) ms_out[q] = t[q];
   } else {
     rc = hip_fail(e, "event create");
   }

@@ -56,6 +56,8 @@ constexpr int kSeg = 64;
 enum Field {
   VX = 0, VY, VZ, SXX, SYY, SZZ, SXY, SXZ, SYZ, RXX, RYY, RZZ, RXY, RXZ, RYZ, kNState
 };
+// The first kNOut fields (v and the normal stresses) can be double-buffered.
+constexpr int kNOut = 6;
 // 18 CPML memories: 9 for the stress derivatives of the velocity update and 9
 // for the velocity derivatives of the stress update.
 constexpr int kNPsi = 18;
@@ -79,7 +81,11 @@ struct StepArgs {
   const float *lut;       // kLutW floats per material
   int n_mat;              // materials in lut
   PmlTab pml;
-  float *f[kNState];      // padded state arrays
+  float *f[kNState];      // padded state arrays (read; shear stresses and memories
+                          // are also written in place)
+  float *fo[kNOut];       // where the velocity (VX..VZ) and normal-stress
+                          // (SXX..SZZ) updates write: f itself (in place) or
+                          // the other buffer of a double-buffered pair
   float *psi[kNPsi];      // padded CPML memories (touched in the layer only)
   const float2 *src;      // [ny][nx] source plane
   float *peak;            // [nz][ny][nx]

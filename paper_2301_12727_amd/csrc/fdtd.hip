@@ -148,7 +148,8 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
   const uint32_t P = (uint32_t)g.pitch, PL = (uint32_t)g.plane, P4 = 4 * P, PL4 = 4 * PL;
   const float *sxx = A.f[SXX], *syy = A.f[SYY], *szz = A.f[SZZ];
   const float *sxy = A.f[SXY], *sxz = A.f[SXZ], *syz = A.f[SYZ];
-  float *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
+  const float *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
+  float *vxw = A.fo[VX], *vyw = A.fo[VY], *vzw = A.fo[VZ];
   const uint8_t *idx = A.idx;
   const uint32_t so = (uint32_t)(j * g.nx + i) * 8u;
   const bool px = in_layer(i, g.nx, g.L), py = in_layer(j, g.ny, g.L);
@@ -176,10 +177,10 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
       if (px) d1 = cpml_b(A.psi[0], o, q0, tx.z, tx.w, d1);
       if (py) e2 = cpml_b(A.psi[4], o, q4, ty.z, ty.w, e2);
       if (pz) f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
-      stb(vx, o, fmaf(b, d1, vxo));
-      stb(vy, o, fmaf(b, e2, vyo));
+      stb(vxw, o, fmaf(b, d1, vxo));
+      stb(vyw, o, fmaf(b, e2, vyo));
       if (on_src) f3 += src_force(src_c, src_s, sq);
-      stb(vz, o, fmaf(b, f3, vzo));
+      stb(vzw, o, fmaf(b, f3, vzo));
       continue;
     }
     const int m0 = ldi(idx, c), mx = ldi(idx, c + 1), my = ldi(idx, c + P), mz = ldi(idx, c + PL);
@@ -210,11 +211,11 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
       e3 = cpml_b(A.psi[5], o, q5, tz.x, tz.y, e3);
       f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
     }
-    stb(vx, o, fmaf(bx, d1 + d2 + d3, vxo));
-    stb(vy, o, fmaf(by, e1 + e2 + e3, vyo));
+    stb(vxw, o, fmaf(bx, d1 + d2 + d3, vxo));
+    stb(vyw, o, fmaf(by, e1 + e2 + e3, vyo));
     float fz = f1 + f2 + f3;
     if (on_src) fz += src_force(src_c, src_s, sq);  // traction source on the v_z faces of plane ks
-    stb(vz, o, fmaf(bz, fz, vzo));
+    stb(vzw, o, fmaf(bz, fz, vzo));
   }
 }
 
@@ -253,7 +254,8 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
   const uint32_t P = (uint32_t)g.pitch, PL = (uint32_t)g.plane, P4 = 4 * P, PL4 = 4 * PL;
   const uint32_t QL4 = (uint32_t)(g.ny * g.nx) * 4u;
   const float *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
-  float *sxxp = A.f[SXX], *syyp = A.f[SYY], *szzp = A.f[SZZ];
+  const float *sxxp = A.f[SXX], *syyp = A.f[SYY], *szzp = A.f[SZZ];
+  float *sxxw = A.fo[SXX], *syyw = A.fo[SYY], *szzw = A.fo[SZZ];
   float *sxyp = A.f[SXY], *sxzp = A.f[SXZ], *syzp = A.f[SYZ];
   float *rxxp = A.f[RXX], *ryyp = A.f[RYY], *rzzp = A.f[RZZ];
   float *rxyp = A.f[RXY], *rxzp = A.f[RXZ], *ryzp = A.f[RYZ];
@@ -282,9 +284,9 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
       if (py) eyy = cpml_b(A.psi[10], o, q10, ty.x, ty.y, eyy);
       if (pz) ezz = cpml_b(A.psi[11], o, q11, tz.x, tz.y, ezz);
       const float sn = fmaf(lut[(cl - 1) * kLutW + kPiU], exx + eyy + ezz, so);
-      stb(sxxp, o, sn);
-      stb(syyp, o, sn);
-      stb(szzp, o, sn);
+      stb(sxxw, o, sn);
+      stb(syyw, o, sn);
+      stb(szzw, o, sn);
       if (capture) {
         const float a = fabsf(sn + sn + sn) / 3.f;
         if (a > pk || a != a) stb(A.peak, qo, a);
@@ -338,7 +340,7 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
     edge(sxy, rxy, dyvx + dxvy, e0, ex, ey, edge_in(lut, mxy), ra, rb);
     edge(sxz, rxz, dzvx + dxvz, e0, ex, ez, edge_in(lut, mxz), ra, rb);
     edge(syz, ryz, dzvy + dyvz, e0, ey, ez, edge_in(lut, myz), ra, rb);
-    stb(sxxp, o, sxx); stb(syyp, o, syy); stb(szzp, o, szz);
+    stb(sxxw, o, sxx); stb(syyw, o, syy); stb(szzw, o, szz);
     stb(rxxp, o, rxx); stb(ryyp, o, ryy); stb(rzzp, o, rzz);
     stb(sxyp, o, sxy); stb(sxzp, o, sxz); stb(syzp, o, syz);
     stb(rxyp, o, rxy); stb(rxzp, o, rxz); stb(ryzp, o, ryz);
@@ -396,10 +398,10 @@ struct VelAc {
     if (C.px) d1 = cpml_b(A.psi[0], o, q0, C.tx.z, C.tx.w, d1);
     if (C.py) e2 = cpml_b(A.psi[4], o, q4, C.ty.z, C.ty.w, e2);
     if (pz) f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
-    stb(A.f[VX], o, fmaf(b, d1, vx));
-    stb(A.f[VY], o, fmaf(b, e2, vy));
+    stb(A.fo[VX], o, fmaf(b, d1, vx));
+    stb(A.fo[VY], o, fmaf(b, e2, vy));
     if (src) f3 += src_force(src_c, src_s, sq);
-    stb(A.f[VZ], o, fmaf(b, f3, vz));
+    stb(A.fo[VZ], o, fmaf(b, f3, vz));
   }
 };
 
@@ -479,10 +481,10 @@ struct StrAc {
     if (C.py) eyy = cpml_b(A.psi[10], o, q10, C.ty.x, C.ty.y, eyy);
     if (pz) ezz = cpml_b(A.psi[11], o, q11, tz.x, tz.y, ezz);
     const float sn = fmaf(lut[(cl - 1) * kLutW + kPiU], exx + eyy + ezz, s);
-    stb(A.f[SXX], o, sn);
+    stb(A.fo[SXX], o, sn);
     if (keep) {  // read by an elastic neighbour: keep the three normal stresses equal
-      stb(A.f[SYY], o, sn);
-      stb(A.f[SZZ], o, sn);
+      stb(A.fo[SYY], o, sn);
+      stb(A.fo[SZZ], o, sn);
     }
     if (capture) {
       const float a = fabsf(sn + sn + sn) / 3.f;
@@ -517,6 +519,88 @@ __device__ __forceinline__ void stress_ac_tile(const StepArgs &A, const float *l
     w0 = w1; w1 = w2; w2 = w3; w3 = h;
     h = hn;
     cur = nxt;
+  }
+}
+
+// ------------------------------------------------------------- deep tiles
+// A deep tile (see k_tile_kinds) takes a whole time step in one pass: each
+// cell recomputes the new velocities its stress update needs (v_x at x-2..x+1,
+// v_y at y-2..y+1, v_z at z-2..z+1, the last in a register window along the
+// march) from the current normal stress and velocities, stores its own new
+// velocity and stress, and never waits for another tile.  Inputs come from the
+// current buffers and outputs go to the other ones, so neighbouring tiles may
+// run in any order.  Every recomputed value is the acoustic velocity update
+// of the velocity kernels, operation for operation, so the results equal the
+// two-pass step bit for bit.  It moves 32 bytes per cell update (sigma_xx and
+// v read, written) instead of 48.
+__device__ __forceinline__ float vnew(float vold, float b, float m1, float p0, float p1, float p2) {
+  return fmaf(b, dfw(m1, p0, p1, p2), vold);
+}
+
+__device__ __forceinline__ void deep_tile(const StepArgs &A, const float *lut, int bx, int j, int k0,
+                                          int k1, float src_c, float src_s, int capture) {
+  const Grid &g = A.g;
+  const int i = bx * kSeg + threadIdx.x;  // deep tiles are whole segments and rows
+  const uint32_t P4 = 4u * (uint32_t)g.pitch, PL4 = 4u * (uint32_t)g.plane;
+  const uint32_t QL4 = (uint32_t)(g.ny * g.nx) * 4u;
+  const float *sxx = A.f[SXX], *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
+  ClassColumn col(A, j, bx, k0);
+  const int cl = col.at(k0, k0);  // one fluid class over the tile and its reach
+  const float b = 1.f / lut[(cl - 1) * kLutW + kRhoS];
+  const float piu = lut[(cl - 1) * kLutW + kPiU];
+  const uint32_t so = (uint32_t)(j * g.nx + i) * 8u;
+  const float2 sq = (g.ks >= k0 - 2 && g.ks <= k1)
+                        ? *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(A.src) + so)
+                        : make_float2(0.f, 0.f);
+  uint32_t o = (uint32_t)g.off(i, j, k0) * 4u;
+  uint32_t qo = ((uint32_t)k0 * (uint32_t)(g.ny * g.nx) + (uint32_t)(j * g.nx + i)) * 4u;
+  // sxx of this column at planes k-3 .. k+3 (s0..s6), new v_z at k-2 .. k+1 (w0..w3)
+  float s0 = ldb(sxx, o - 3 * PL4), s1 = ldb(sxx, o - 2 * PL4), s2 = ldb(sxx, o - PL4),
+        s3 = ldb(sxx, o), s4 = ldb(sxx, o + PL4), s5 = ldb(sxx, o + 2 * PL4),
+        s6 = ldb(sxx, o + 3 * PL4);
+  auto vz_face = [&](int kk, float vold, float m1, float p0, float p1, float p2) {
+    float f3 = dfw(m1, p0, p1, p2);
+    if (kk == g.ks) f3 += src_force(src_c, src_s, sq);
+    return fmaf(b, f3, vold);
+  };
+  float w0 = vz_face(k0 - 2, ldb(vz, o - 2 * PL4), s0, s1, s2, s3);
+  float w1 = vz_face(k0 - 1, ldb(vz, o - PL4), s1, s2, s3, s4);
+  float w2 = vz_face(k0, ldb(vz, o), s2, s3, s4, s5);
+  float w3 = vz_face(k0 + 1, ldb(vz, o + PL4), s3, s4, s5, s6);
+  for (int k = k0; k < k1; ++k, o += PL4, qo += QL4) {
+    // x stencil of sxx on this row and plane, y stencil on this column
+    const float xm3 = ldb(sxx, o - 12), xm2 = ldb(sxx, o - 8), xm1 = ldb(sxx, o - 4);
+    const float xp1 = ldb(sxx, o + 4), xp2 = ldb(sxx, o + 8), xp3 = ldb(sxx, o + 12);
+    const float ym3 = ldb(sxx, o - 3 * P4), ym2 = ldb(sxx, o - 2 * P4), ym1 = ldb(sxx, o - P4);
+    const float yp1 = ldb(sxx, o + P4), yp2 = ldb(sxx, o + 2 * P4), yp3 = ldb(sxx, o + 3 * P4);
+    const float ux2 = ldb(vx, o - 8), ux1 = ldb(vx, o - 4), ux0 = ldb(vx, o), uxp = ldb(vx, o + 4);
+    const float uy2 = ldb(vy, o - 2 * P4), uy1 = ldb(vy, o - P4), uy0 = ldb(vy, o),
+                uyp = ldb(vy, o + P4);
+    const bool more = k + 1 < k1;
+    const float s7 = more ? ldb(sxx, o + 4 * PL4) : 0.f;    // plane k + 4
+    const float vzn = more ? ldb(vz, o + 2 * PL4) : 0.f;    // plane k + 2
+    const float pk = capture ? ldb_once(A.peak, qo) : 0.f;
+    // new velocities around the cell (the velocity kernels' acoustic update)
+    const float nx2 = vnew(ux2, b, xm3, xm2, xm1, s3), nx1 = vnew(ux1, b, xm2, xm1, s3, xp1);
+    const float nx0 = vnew(ux0, b, xm1, s3, xp1, xp2), nxp = vnew(uxp, b, s3, xp1, xp2, xp3);
+    const float ny2 = vnew(uy2, b, ym3, ym2, ym1, s3), ny1 = vnew(uy1, b, ym2, ym1, s3, yp1);
+    const float ny0 = vnew(uy0, b, ym1, s3, yp1, yp2), nyp = vnew(uyp, b, s3, yp1, yp2, yp3);
+    // stress update (the acoustic stress kernels' arithmetic)
+    const float exx = dbw(nx2, nx1, nx0, nxp), eyy = dbw(ny2, ny1, ny0, nyp), ezz = dbw(w0, w1, w2, w3);
+    const float sn = fmaf(piu, exx + eyy + ezz, s3);
+    stb(A.fo[VX], o, nx0);
+    stb(A.fo[VY], o, ny0);
+    stb(A.fo[VZ], o, w2);
+    stb(A.fo[SXX], o, sn);
+    if (capture) {
+      const float a = fabsf(sn + sn + sn) / 3.f;
+      if (a > pk || a != a) stb(A.peak, qo, a);
+    }
+    if (more) {
+      const float w4 = vz_face(k + 2, vzn, s4, s5, s6, s7);
+      s0 = s1; s1 = s2; s2 = s3; s3 = s4; s4 = s5; s5 = s6; s6 = s7;
+      w0 = w1; w1 = w2; w2 = w3; w3 = w4;
+    }
   }
 }
 
@@ -583,16 +667,33 @@ __global__ void __launch_bounds__(kSeg * kRows)
   stress_ac_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.capture);
 }
 
+__global__ void __launch_bounds__(kSeg * kRows)
+    k_step_deep(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
+  const int n = *count;
+  if ((int)blockIdx.x >= n) return;
+  stage_lut(s_lut, A.lut, A.n_mat);
+  __syncthreads();
+  int bx, by, k0, k1;
+  tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
+  deep_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s, A.capture);
+}
+
 // Tile kinds of a single solve: 1 when every row segment of the tile has a
-// fluid class on every plane of its chunk (acoustic tile), else 0.
+// fluid class on every plane of its chunk (acoustic tile), 2 when moreover the
+// tile and its reach for the fused step (3 cells in x, 3 rows and 3 planes
+// around it) lie outside the absorbing layer and inside the grid and all of
+// its segments, those of the neighbouring x segments included, hold one and
+// the same fluid class (deep tile), else 0.
+constexpr int kReach = 3;
 __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
+  const Grid &g = A.g;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A.n_tiles; t += gridDim.x * blockDim.x) {
     int bx, by, k0, k1;
     tile_coords(A, t, bx, by, k0, k1);
     bool ac = true;
     for (int r = 0; ac && r < kRows; ++r) {
       const int j = by * kRows + r;
-      if (j >= A.g.ny) break;
+      if (j >= g.ny) break;
       const uint8_t *colp = A.cls + ((long long)j * A.nseg + bx) * A.kpad;
       for (int k = k0; k < k1; ++k)
         if (colp[k] == 0) {
@@ -600,44 +701,70 @@ __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
           break;
         }
     }
-    kind[t] = ac ? 1 : 0;
+    int kd = ac ? 1 : 0;
+    const int i0 = bx * kSeg, j0 = by * kRows;
+    if (ac && i0 - kReach >= g.L && i0 + kSeg - 1 + kReach < g.nx - g.L && j0 - kReach >= g.L &&
+        j0 + kRows - 1 + kReach < g.ny - g.L && k0 - kReach >= g.L && k1 - 1 + kReach < g.nz - g.L) {
+      const int c = A.cls[((long long)j0 * A.nseg + bx) * A.kpad + k0];
+      bool deep = true;
+      for (int sg = bx - 1; deep && sg <= bx + 1; ++sg)
+        for (int j = j0 - kReach; deep && j < j0 + kRows + kReach; ++j) {
+          const uint8_t *colp = A.cls + ((long long)j * A.nseg + sg) * A.kpad;
+          for (int k = k0 - kReach; k < k1 + kReach; ++k)
+            if (colp[k] != c) {
+              deep = false;
+              break;
+            }
+        }
+      if (deep) kd = 2;
+    }
+    kind[t] = (uint8_t)kd;
   }
 }
 
 // Stable split of the tile ids by kind: lists[0] acoustic, lists[1] general,
-// counts[0..1] their lengths.  One block; a chunked block-wide prefix sum.
+// lists[2] deep; counts[0..2] their lengths.  One block; chunked block-wide
+// prefix sums.
 constexpr int kListThreads = 1024;
 __global__ void __launch_bounds__(kListThreads)
     k_tile_lists(const uint8_t *__restrict__ kind, int n, int *__restrict__ list_ac,
-                 int *__restrict__ list_gen, int *__restrict__ counts) {
-  __shared__ int sc[kListThreads];
-  __shared__ int base;
+                 int *__restrict__ list_gen, int *__restrict__ list_deep, int *__restrict__ counts) {
+  __shared__ int sa[kListThreads], sd[kListThreads];
+  __shared__ int base_a, base_d;
   const int t = threadIdx.x;
-  if (t == 0) base = 0;
+  if (t == 0) base_a = base_d = 0;
   __syncthreads();
   for (int c0 = 0; c0 < n; c0 += kListThreads) {
     const int id = c0 + t;
-    const int f = (id < n && kind[id]) ? 1 : 0;
-    sc[t] = f;
+    const int kd = id < n ? kind[id] : 0;
+    const int fa = kd == 1 ? 1 : 0, fd = kd == 2 ? 1 : 0;
+    sa[t] = fa;
+    sd[t] = fd;
     __syncthreads();
-    for (int o = 1; o < kListThreads; o <<= 1) {  // inclusive Hillis-Steele scan
-      const int v = t >= o ? sc[t - o] : 0;
+    for (int o = 1; o < kListThreads; o <<= 1) {  // inclusive Hillis-Steele scans
+      const int va = t >= o ? sa[t - o] : 0, vd = t >= o ? sd[t - o] : 0;
       __syncthreads();
-      sc[t] += v;
+      sa[t] += va;
+      sd[t] += vd;
       __syncthreads();
     }
-    const int before = base + sc[t] - f;  // acoustic tiles before id
+    const int ba = base_a + sa[t] - fa, bd = base_d + sd[t] - fd;  // earlier tiles of each kind
     if (id < n) {
-      if (f) list_ac[before] = id;
-      else list_gen[id - before] = id;
+      if (fa) list_ac[ba] = id;
+      else if (fd) list_deep[bd] = id;
+      else list_gen[id - ba - bd] = id;
     }
     __syncthreads();
-    if (t == kListThreads - 1) base += sc[t];
+    if (t == kListThreads - 1) {
+      base_a += sa[t];
+      base_d += sd[t];
+    }
     __syncthreads();
   }
   if (t == 0) {
-    counts[0] = base;
-    counts[1] = n - base;
+    counts[0] = base_a;
+    counts[1] = n - base_a - base_d;
+    counts[2] = base_d;
   }
 }
 
@@ -963,6 +1090,14 @@ hipError_t launch_velocity(const StepArgs &a, const int *const *lists, const int
   return hipGetLastError();
 }
 
+// Fused step of the deep tiles (lists[2], counts[2]).
+hipError_t launch_deep(const StepArgs &a, const int *const *lists, const int *counts,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_step_deep, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a,
+                     lists[2], counts + 2);
+  return hipGetLastError();
+}
+
 hipError_t launch_stress(const StepArgs &a, const int *const *lists, const int *counts, int which,
                          hipStream_t s) {
   if (which == 0)
@@ -989,7 +1124,7 @@ hipError_t launch_tile_lists(const StepArgs &a, uint8_t *kind, int *const *lists
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_tile_kinds, dim3(blocks), dim3(256), 0, s, a, kind);
   hipLaunchKernelGGL(k_tile_lists, dim3(1), dim3(kListThreads), 0, s, kind, a.n_tiles, lists[0],
-                     lists[1], counts);
+                     lists[1], lists[2], counts);
   return hipGetLastError();
 }
 
