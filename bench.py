@@ -51,15 +51,37 @@ KERNELS = ("velocity_ac", "velocity", "stress_ac", "stress", "step_deep")
 REACH = 3   # cells around a deep tile that its fused step reads
 
 
+def keep_flags(classes):
+    """Segment keep flags [nz][ny][nseg]: an acoustic segment within rows j-2..j+1
+    or planes k-2..k+1 of an elastic (class 0) segment of the same x segment
+    stores sigma_yy and sigma_zz too (the elastic one reads them)."""
+    import numpy as np
+    el = classes == 0
+    near = np.zeros_like(el)
+    for d in (-2, -1, 0, 1):
+        if d < 0:
+            near[:, -d:] |= el[:, :d]
+            near[-d:] |= el[:d]
+        elif d > 0:
+            near[:, :-d] |= el[:, d:]
+            near[:-d] |= el[d:]
+        else:
+            near |= el
+    return near
+
+
 def tile_kinds(case, info, classes):
     """Kind of every tile as the library assigns it: 0 general, 1 acoustic,
-    2 deep (acoustic, inside the grid and outside the layer with REACH cells
-    around it, one fluid class over the tile, its reach and the neighbouring
-    x segments).  Returns kinds [nz-chunks][row blocks][segments]."""
+    2 deep: an acoustic tile that, with REACH cells around it, lies inside the
+    grid and outside the layer, whose reach holds its fluid only (segment
+    classes one row and one plane around it, the material map for the third
+    cell in x) and whose sigma_yy / sigma_zz no elastic segment reads (keep
+    flags 0).  Returns kinds [nz-chunks][row blocks][segments]."""
     import numpy as np
     nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
     R, K = int(info["tile_rows"]), int(info["tile_planes"])
     seg = classes != 0
+    keep = keep_flags(classes)
     nseg = seg.shape[2]
     nby, nzc = -(-ny // R), -(-nz // K)
     pad = np.ones((nzc * K, nby * R, nseg), dtype=bool)
@@ -71,8 +93,13 @@ def tile_kinds(case, info, classes):
         if not (i0 - REACH >= L and i0 + 63 + REACH < nx - L and j0 - REACH >= L
                 and j0 + R - 1 + REACH < ny - L and k0 - REACH >= L and k1 - 1 + REACH < nz - L):
             continue
-        blk = classes[k0 - REACH:k1 + REACH, j0 - REACH:j0 + R + REACH, bx - 1:bx + 2]
-        if (blk == classes[k0, j0, bx]).all():
+        c = classes[k0, j0, bx]
+        if not (classes[k0 - 1:k1 + 1, j0 - 1:j0 + R + 1, bx] == c).all():
+            continue
+        if keep[k0:k1, j0:j0 + R, bx].any():
+            continue
+        shell = case.mat[k0 - REACH:k1 + REACH, j0 - REACH:j0 + R + REACH, [i0 - REACH, i0 + 63 + REACH]]
+        if (shell == c - 1).all():
             kind[kc, by, bx] = 2
     return kind
 
@@ -104,19 +131,7 @@ def algorithmic_bytes(case, info, classes) -> dict:
     kind = tile_kinds(case, info, classes)
     cell_kind = np.repeat(np.repeat(np.repeat(kind, K, 0)[:nz], R, 1)[:, :ny], 64, 2)[:, :, :nx]
     fluid = np.repeat(seg, 64, axis=2)[:, :, :nx]
-    # keep flags: an acoustic segment within 2 rows or 2 planes of an elastic
-    # (class 0) segment of the same x segment stores sigma_yy and sigma_zz too
-    el = ~seg
-    near = np.zeros_like(el)
-    for d in (-2, -1, 0, 1):
-        if d < 0:
-            near[:, -d:] |= el[:, :d]
-            near[-d:] |= el[:d]
-        elif d > 0:
-            near[:, :-d] |= el[:, d:]
-            near[:-d] |= el[d:]
-        else:
-            near |= el
+    near = keep_flags(classes)
     keep = np.repeat(near, 64, axis=2)[:, :, :nx]
     axes_in_layer = np.zeros((nz, ny, nx), dtype=np.int8)
     for a, n in ((2, nx), (1, ny), (0, nz)):

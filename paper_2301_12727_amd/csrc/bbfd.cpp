@@ -117,6 +117,8 @@ struct bbfd_plan {
   int n_tiles = 0;
   std::mutex mu;
   hipStream_t cap_stream = nullptr;
+  hipStream_t side_stream = nullptr;  // second branch of the captured steps
+  hipEvent_t fork = nullptr, join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   const void *key[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -396,13 +398,24 @@ int enqueue_epilogue(const bbfd_plan *pl, float *peak, char *ws, hipStream_t s) 
   return BBFD_OK;
 }
 
+// Make `to` wait for the work enqueued so far on `from`.
+hipError_t link(hipStream_t from, hipStream_t to, hipEvent_t ev) {
+  hipError_t e = hipEventRecord(ev, from);
+  return e != hipSuccess ? e : hipStreamWaitEvent(to, ev, 0);
+}
+
 // Enqueue one whole solve on s (no synchronisation).  With ev != NULL (direct
 // launches only), ev[2 (5n + q)] / ev[2 (5n + q) + 1] bracket kernel q of step
 // n (q: 0 acoustic velocity, 1 general velocity, 2 acoustic stress, 3 general
-// stress, 4 fused step of the deep tiles).
+// stress, 4 fused step of the deep tiles).  With side != NULL (graph capture
+// only, under the plan's lock), each step forks in two branches: the fused
+// step of the deep tiles runs on `side` beside the velocity kernels, then the
+// acoustic stress kernel beside the general one; the kernels of a branch pair
+// touch disjoint outputs, so running them side by side fills the tail of one
+// with blocks of the other.
 constexpr int kStepKernels = 5;
 int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
-                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr) {
+                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr, hipStream_t side = nullptr) {
   const bbfd_problem &p = pl->prob;
   int rc = enqueue_prologue(pl, mat, peak, ws, s);
   if (rc) return rc;
@@ -434,6 +447,20 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
       as.fo[f] = nxt[f];
       ad.f[f] = cur[f];
       ad.fo[f] = nxt[f];
+    }
+    if (side) {
+      if ((e = link(s, side, pl->fork)) != hipSuccess ||
+          (e = launch_deep(ad, lists, counts, side)) != hipSuccess ||
+          (e = launch_velocity(av, lists, counts, 0, s)) != hipSuccess ||
+          (e = launch_velocity(av, lists, counts, 1, s)) != hipSuccess ||
+          (e = link(side, s, pl->join)) != hipSuccess ||
+          (e = link(s, side, pl->fork)) != hipSuccess ||
+          (e = launch_stress(as, lists, counts, 0, side)) != hipSuccess ||
+          (e = launch_stress(as, lists, counts, 1, s)) != hipSuccess ||
+          (e = link(side, s, pl->join)) != hipSuccess)
+        return hip_fail(e, "step launch");
+      for (int f = 0; f < kNOut; ++f) std::swap(cur[f], nxt[f]);
+      continue;
     }
     // order: both velocity kernels and the fused step (all read only cur),
     // then the stress kernels (they read the new velocity of every tile)
@@ -561,6 +588,9 @@ void bbfd_plan_destroy(bbfd_plan *pl) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  if (pl->side_stream) (void)hipStreamDestroy(pl->side_stream);
+  if (pl->fork) (void)hipEventDestroy(pl->fork);
+  if (pl->join) (void)hipEventDestroy(pl->join);
   if (pl->h_lut) (void)hipHostFree(pl->h_lut);
   if (pl->h_pml) (void)hipHostFree(pl->h_pml);
   delete pl;
@@ -711,9 +741,17 @@ int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float
     if (!pl->cap_stream &&
         (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "capture stream");
+    if (!pl->side_stream &&
+        (e = hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking)) != hipSuccess)
+      return hip_fail(e, "capture stream");
+    if (!pl->fork && (e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "capture event");
+    if (!pl->join && (e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "capture event");
     if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(e, "begin capture");
-    rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, pl->cap_stream);
+    rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, pl->cap_stream, nullptr,
+                       pl->side_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(pl->cap_stream, &g);
     if (rc) {

@@ -679,11 +679,18 @@ __global__ void __launch_bounds__(kSeg * kRows)
 }
 
 // Tile kinds of a single solve: 1 when every row segment of the tile has a
-// fluid class on every plane of its chunk (acoustic tile), 2 when moreover the
-// tile and its reach for the fused step (3 cells in x, 3 rows and 3 planes
-// around it) lie outside the absorbing layer and inside the grid and all of
-// its segments, those of the neighbouring x segments included, hold one and
-// the same fluid class (deep tile), else 0.
+// fluid class on every plane of its chunk (acoustic tile), 2 (deep tile) when
+// moreover
+//  * the tile and its reach for the fused step (3 cells in x, 3 rows and 3
+//    planes around it) lie inside the grid and outside the absorbing layer,
+//  * every cell of that reach holds the tile's fluid: the classes of the
+//    segments one row and one plane around the tile cover it up to two cells
+//    beyond their segment in x, and the index map is read for the third, and
+//  * no elastic segment reads sigma_yy or sigma_zz of the tile (keep flags 0:
+//    the fused step stores sigma_xx alone),
+// else 0.  Within that reach every other kernel's velocity update reduces to
+// the acoustic one (shear stresses of fluid edges are zero), so the fused
+// step's recomputed neighbours equal the values the neighbouring tiles store.
 constexpr int kReach = 3;
 __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
   const Grid &g = A.g;
@@ -707,15 +714,22 @@ __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
         j0 + kRows - 1 + kReach < g.ny - g.L && k0 - kReach >= g.L && k1 - 1 + kReach < g.nz - g.L) {
       const int c = A.cls[((long long)j0 * A.nseg + bx) * A.kpad + k0];
       bool deep = true;
-      for (int sg = bx - 1; deep && sg <= bx + 1; ++sg)
-        for (int j = j0 - kReach; deep && j < j0 + kRows + kReach; ++j) {
-          const uint8_t *colp = A.cls + ((long long)j * A.nseg + sg) * A.kpad;
-          for (int k = k0 - kReach; k < k1 + kReach; ++k)
-            if (colp[k] != c) {
-              deep = false;
-              break;
-            }
-        }
+      for (int j = j0 - 1; deep && j <= j0 + kRows; ++j) {
+        const long long col = ((long long)j * A.nseg + bx) * A.kpad;
+        const bool inner = j >= j0 && j < j0 + kRows;
+        for (int k = k0 - 1; k <= k1; ++k)
+          if (A.cls[col + k] != c || (inner && k >= k0 && k < k1 && A.keep[col + k] != 0)) {
+            deep = false;
+            break;
+          }
+      }
+      for (int k = k0 - kReach; deep && k < k1 + kReach; ++k)
+        for (int j = j0 - kReach; j < j0 + kRows + kReach; ++j)
+          if (A.idx[g.off(i0 - kReach, j, k)] != c - 1 ||
+              A.idx[g.off(i0 + kSeg - 1 + kReach, j, k)] != c - 1) {
+            deep = false;
+            break;
+          }
       if (deep) kd = 2;
     }
     kind[t] = (uint8_t)kd;
