@@ -32,9 +32,126 @@ __device__ __forceinline__ long long b_off(const GemmArgs &g, int k, int n) {
   return (long long)(k - seg * g.b_seg_k) * g.sBk + (long long)n * g.sBn + seg * g.b_seg_off;
 }
 
+// Staging of one 64 x 32 operand tile.  Mode 0: one element per load, any
+// strides.  Mode 1: four consecutive k per load (k unit-stride).  Mode 2: four
+// consecutive m (or n) per load.  Modes 1 and 2 need the vectorised axis'
+// extent, the other strides and the base 16-byte aligned (checked on the host,
+// see launch_gemm), so a float4 is either wholly inside the operand or wholly
+// outside it.  Every thread holds 8 values (two float4) of the next tile in
+// registers while the matrix cores work on the current one.
+struct Stage {
+  float v[8];
+};
+
+template <int MODE>
+__device__ __forceinline__ void load_a(const GemmArgs &g, const float *A, int m0, int k0, int t,
+                                       Stage &r) {
+  if (MODE == 0) {
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + kThreads * q;
+      int m, k;
+      if (g.a_kfast) { m = e >> 5; k = e & 31; } else { m = e & 63; k = e >> 6; }
+      const int gm = m0 + m, gk = k0 + k;
+      r.v[q] = (gm < g.M && gk < g.K) ? A[a_off(g, gm, gk)] : 0.f;
+    }
+  } else {
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + kThreads * q;
+      int m, k;
+      if (MODE == 1) { m = e >> 3; k = (e & 7) << 2; } else { k = e >> 4; m = (e & 15) << 2; }
+      const int gm = m0 + m, gk = k0 + k;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gm < g.M && gk < g.K) x = *reinterpret_cast<const float4 *>(A + a_off(g, gm, gk));
+      r.v[4 * q] = x.x; r.v[4 * q + 1] = x.y; r.v[4 * q + 2] = x.z; r.v[4 * q + 3] = x.w;
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_a(__bf16 (*As)[kBK + kPad], int t, const Stage &r,
+                                        const GemmArgs &g) {
+  if (MODE == 0) {
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + kThreads * q;
+      int m, k;
+      if (g.a_kfast) { m = e >> 5; k = e & 31; } else { m = e & 63; k = e >> 6; }
+      As[m][k] = (__bf16)r.v[q];
+    }
+  } else {
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + kThreads * q;
+      if (MODE == 1) {
+        const int m = e >> 3, k = (e & 7) << 2;
+        for (int i = 0; i < 4; ++i) As[m][k + i] = (__bf16)r.v[4 * q + i];
+      } else {
+        const int k = e >> 4, m = (e & 15) << 2;
+        for (int i = 0; i < 4; ++i) As[m + i][k] = (__bf16)r.v[4 * q + i];
+      }
+    }
+  }
+}
+
+// B tile (32 k x 64 n), staged as Bs[n][k].  Mode 1: four consecutive n per
+// load (n unit-stride); mode 2: four consecutive k.
+template <int MODE>
+__device__ __forceinline__ void load_b(const GemmArgs &g, const float *B, int n0, int k0, int t,
+                                       Stage &r) {
+  if (MODE == 0) {
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + kThreads * q;
+      int n, k;
+      if (g.b_nfast) { n = e & 63; k = e >> 6; } else { n = e >> 5; k = e & 31; }
+      const int gn = n0 + n, gk = k0 + k;
+      r.v[q] = (gn < g.N && gk < g.K) ? B[b_off(g, gk, gn)] : 0.f;
+    }
+  } else {
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + kThreads * q;
+      int n, k;
+      if (MODE == 1) { k = e >> 4; n = (e & 15) << 2; } else { n = e >> 3; k = (e & 7) << 2; }
+      const int gn = n0 + n, gk = k0 + k;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (gn < g.N && gk < g.K) x = *reinterpret_cast<const float4 *>(B + b_off(g, gk, gn));
+      r.v[4 * q] = x.x; r.v[4 * q + 1] = x.y; r.v[4 * q + 2] = x.z; r.v[4 * q + 3] = x.w;
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void store_b(__bf16 (*Bs)[kBK + kPad], int t, const Stage &r,
+                                        const GemmArgs &g) {
+  if (MODE == 0) {
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + kThreads * q;
+      int n, k;
+      if (g.b_nfast) { n = e & 63; k = e >> 6; } else { n = e >> 5; k = e & 31; }
+      Bs[n][k] = (__bf16)r.v[q];
+    }
+  } else {
+    for (int q = 0; q < 2; ++q) {
+      const int e = t + kThreads * q;
+      if (MODE == 1) {
+        const int k = e >> 4, n = (e & 15) << 2;
+        for (int i = 0; i < 4; ++i) Bs[n + i][k] = (__bf16)r.v[4 * q + i];
+      } else {
+        const int n = e >> 3, k = (e & 7) << 2;
+        for (int i = 0; i < 4; ++i) Bs[n][k + i] = (__bf16)r.v[4 * q + i];
+      }
+    }
+  }
+}
+
+// LDS: the two operand tiles during the K loop; the 64 x 64 FP32 result
+// (transposed) in the column-major epilogue, after the loop.
+constexpr int kOpBytes = kBM * (kBK + kPad) * 2;
+constexpr int kCPitch = kBM + 4;
+constexpr int kSmem = kBN * kCPitch * 4 > 2 * kOpBytes ? kBN * kCPitch * 4 : 2 * kOpBytes;
+
+template <int AMODE, int BMODE>
 __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
-  __shared__ __bf16 As[kBM][kBK + kPad];  // [m][k]
-  __shared__ __bf16 Bs[kBN][kBK + kPad];  // [n][k]
+  __shared__ __align__(16) char smem[kSmem];
+  auto As = reinterpret_cast<__bf16 (*)[kBK + kPad]>(smem);             // [m][k]
+  auto Bs = reinterpret_cast<__bf16 (*)[kBK + kPad]>(smem + kOpBytes);  // [n][k]
   const int b = blockIdx.z;
   const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
   const float *A = g.A + (long long)b * g.sAb;
@@ -44,26 +161,17 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   f32x16 acc;
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  Stage ra, rb;
+  load_a<AMODE>(g, A, m0, 0, t, ra);
+  load_b<BMODE>(g, B, n0, 0, t, rb);
   for (int k0 = 0; k0 < g.K; k0 += kBK) {
-    // stage A (64 x 32) and B (32 x 64): 8 elements per thread each, the
-    // unit-stride axis mapped to consecutive threads
-    for (int r = 0; r < 8; ++r) {
-      const int e = t + kThreads * r;
-      int m, k;
-      if (g.a_kfast) { m = e >> 5; k = e & 31; } else { m = e & 63; k = e >> 6; }
-      const int gm = m0 + m, gk = k0 + k;
-      const float v = (gm < g.M && gk < g.K) ? A[a_off(g, gm, gk)] : 0.f;
-      As[m][k] = (__bf16)v;
-    }
-    for (int r = 0; r < 8; ++r) {
-      const int e = t + kThreads * r;
-      int n, k;
-      if (g.b_nfast) { n = e & 63; k = e >> 6; } else { n = e >> 5; k = e & 31; }
-      const int gn = n0 + n, gk = k0 + k;
-      const float v = (gn < g.N && gk < g.K) ? B[b_off(g, gk, gn)] : 0.f;
-      Bs[n][k] = (__bf16)v;
-    }
+    store_a<AMODE>(As, t, ra, g);
+    store_b<BMODE>(Bs, t, rb, g);
     __syncthreads();
+    if (k0 + kBK < g.K) {  // next tile's loads fly while the matrix cores work
+      load_a<AMODE>(g, A, m0, k0 + kBK, t, ra);
+      load_b<BMODE>(g, B, n0, k0 + kBK, t, rb);
+    }
     for (int kk = 0; kk < kBK; kk += 16) {
       // lane l holds rows/cols l % 32 and the 8 consecutive k of half l / 32
       const int kq = kk + 8 * (lane >> 5);
@@ -74,6 +182,32 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
     __syncthreads();
   }
   float *C = g.C + (long long)b * g.sCb;
+  if (g.c_mfast) {
+    // column-major C: transpose the tile through LDS, then each thread writes
+    // four consecutive rows of one column as a float4
+    auto Cs = reinterpret_cast<float (*)[kCPitch]>(smem);  // [n][m]
+    for (int r = 0; r < 16; ++r)
+      Cs[wn + (lane & 31)][wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = acc[r];
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + kThreads * q;
+      const int n = e >> 4, m = (e & 15) << 2;
+      const int gn = n0 + n, gm = m0 + m;
+      if (gn >= g.N || gm >= g.M) continue;
+      const float4 c = *reinterpret_cast<const float4 *>(&Cs[n][m]);
+      float4 *dst = reinterpret_cast<float4 *>(C + (long long)gn * g.sCn + gm);
+      float4 v = make_float4(g.alpha * c.x, g.alpha * c.y, g.alpha * c.z, g.alpha * c.w);
+      if (g.beta != 0.f) {
+        const float4 o = *dst;
+        v.x += g.beta * o.x; v.y += g.beta * o.y; v.z += g.beta * o.z; v.w += g.beta * o.w;
+      }
+      if (g.bias) {
+        v.x += g.bias[gm]; v.y += g.bias[gm + 1]; v.z += g.bias[gm + 2]; v.w += g.bias[gm + 3];
+      }
+      *dst = v;
+    }
+    return;
+  }
   const int col = n0 + wn + (lane & 31);
   if (col >= g.N) return;
   for (int r = 0; r < 16; ++r) {
@@ -332,10 +466,41 @@ hipError_t launch_features(const uint8_t *mat, const float2 *table, int n_table,
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const GemmArgs &g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0) return hipSuccess;
+static bool al4(long long v) { return v % 4 == 0; }
+
+// Picks the staging modes: float4 loads along an operand's unit-stride axis
+// when that axis' extent, the other strides, the segment offset and the base
+// are all multiples of four floats; the column-major epilogue when C is
+// unit-stride along m under the same conditions.
+hipError_t launch_gemm(const GemmArgs &g0, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return hipSuccess;
+  GemmArgs g = g0;
+  const bool a16 = (uintptr_t)g.A % 16 == 0 && al4(g.sAb) && al4(g.a_seg_off) &&
+                   (g.a_seg_k >= g.K || al4(g.a_seg_k));
+  const bool b16 = (uintptr_t)g.B % 16 == 0 && al4(g.sBb) && al4(g.b_seg_off) &&
+                   (g.b_seg_k >= g.K || al4(g.b_seg_k));
+  int am = 0, bm = 0;
+  if (a16 && g.sAk == 1 && al4(g.K) && al4(g.sAm)) am = 1;
+  else if (a16 && g.sAm == 1 && al4(g.M) && al4(g.sAk)) am = 2;
+  if (b16 && g.sBn == 1 && al4(g.N) && al4(g.sBk)) bm = 1;
+  else if (b16 && g.sBk == 1 && al4(g.K) && al4(g.sBn)) bm = 2;
+  g.c_mfast = (g.sCm == 1 && g.sCn != 1 && al4(g.M) && al4(g.sCn) && al4(g.sCb) &&
+               (uintptr_t)g.C % 16 == 0) ? 1 : 0;
   dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, g.batch);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(kThreads), 0, s, g);
+  dim3 blk(kThreads);
+#define BBSUR_GEMM(AM, BM) hipLaunchKernelGGL((k_gemm<AM, BM>), grid, blk, 0, s, g)
+  switch (am * 3 + bm) {
+    case 0: BBSUR_GEMM(0, 0); break;
+    case 1: BBSUR_GEMM(0, 1); break;
+    case 2: BBSUR_GEMM(0, 2); break;
+    case 3: BBSUR_GEMM(1, 0); break;
+    case 4: BBSUR_GEMM(1, 1); break;
+    case 5: BBSUR_GEMM(1, 2); break;
+    case 6: BBSUR_GEMM(2, 0); break;
+    case 7: BBSUR_GEMM(2, 1); break;
+    default: BBSUR_GEMM(2, 2); break;
+  }
+#undef BBSUR_GEMM
   return hipGetLastError();
 }
 

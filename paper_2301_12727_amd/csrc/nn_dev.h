@@ -18,7 +18,8 @@ struct GemmArgs {
   long long sBb, sBk, sBn, b_seg_off;
   long long sCb, sCm, sCn;
   int a_seg_k, b_seg_k;
-  int a_kfast, b_nfast;  // which axis is unit-stride (staging order)
+  int a_kfast, b_nfast;  // which axis is unit-stride (staging order of the scalar path)
+  int c_mfast;           // set by the launcher: column-major epilogue
   float alpha, beta;
 };
 

@@ -27,9 +27,15 @@ def bf16(a):
     return r.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+# "n" stores an operand as written, "t" transposed; a third letter "c" stores C
+# column-major.  Sizes that are multiples of 4 take the float4 staging paths
+# (and the transposed epilogue for "c"), the others the element-wise ones.
 @pytest.mark.parametrize("M,N,K,batch,trans", [(64, 64, 32, 1, "nn"), (50, 70, 45, 3, "nn"),
                                                 (33, 17, 130, 2, "tn"), (1, 300, 7, 2, "nt"),
-                                                (128, 96, 64, 1, "tt")])
+                                                (128, 96, 64, 1, "tt"), (256, 16, 64, 3, "nnc"),
+                                                (200, 132, 96, 2, "ttc"), (96, 40, 36, 2, "tnc"),
+                                                (52, 200, 100, 1, "ntc"), (68, 20, 8, 2, "nt"),
+                                                (50, 36, 44, 2, "nnc")])
 def test_gemm_matches_bf16_reference(M, N, K, batch, trans):
     rng = np.random.default_rng(M * 1000 + N)
     A = rng.normal(size=(batch, M, K)).astype(np.float32)
@@ -42,12 +48,16 @@ def test_gemm_matches_bf16_reference(M, N, K, batch, trans):
     a_str = (M * K, 1, M) if trans[0] == "t" else (M * K, K, 1)
     b_str = (K * N, 1, K) if trans[1] == "t" else (K * N, N, 1)
     tA, tB = torch.from_numpy(Ad).cuda(), torch.from_numpy(Bd).cuda()
-    tC = torch.from_numpy(C0.copy()).cuda()
+    colmajor = trans[2:] == "c"
+    tC = torch.from_numpy(np.ascontiguousarray(C0.transpose(0, 2, 1) if colmajor else C0)).cuda()
+    c_str = (M * N, 1, M) if colmajor else (M * N, N, 1)
     tb = torch.from_numpy(bias).cuda()
-    sg.gemm(tA, a_str, tB, b_str, tC, (M * N, N, 1), M, N, K, batch, alpha=1.5, beta=0.5, bias=tb)
+    sg.gemm(tA, a_str, tB, b_str, tC, c_str, M, N, K, batch, alpha=1.5, beta=0.5, bias=tb)
     torch.cuda.synchronize()
     want = 1.5 * np.einsum("bmk,bkn->bmn", bf16(A), bf16(B)) + 0.5 * C0 + bias[None, :, None]
     got = tC.cpu().numpy()
+    if colmajor:
+        got = got.transpose(0, 2, 1)
     err = np.abs(got - want).max() / np.abs(want).max()
     say(f"[gemm] {M}x{N}x{K} b{batch} {trans}: max rel {err:.2e}")
     assert err < 1e-5
