@@ -252,18 +252,20 @@ __global__ void k_fill(float *__restrict__ p, long long n, float v) {
 // Per-mode complex channel mixing.  U, V: [b][ch][2][Q] (real plane, then
 // imaginary plane); R: [2][Q][C][O].
 //   V[b][o][q] = sum_c R[q][c][o] U[b][c][q]
+// One thread per (b, q, o), o fastest: a wave reads R[q][c][.] as whole rows
+// and U[b][c][q] as one broadcast value per mode.
 __global__ void k_mix(const float *__restrict__ U, const float *__restrict__ R,
                       float *__restrict__ V, int B, int C, int O, int Q) {
   const long long total = (long long)B * O * Q;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const int q = (int)(t % Q);
-    const int o = (int)((t / Q) % O);
-    const int b = (int)(t / ((long long)Q * O));
-    float vr = 0.f, vi = 0.f;
-    const float *u = U + (long long)b * C * 2 * Q + q;
+    const int o = (int)(t % O);
+    const int q = (int)((t / O) % Q);
+    const int b = (int)(t / ((long long)O * Q));
     const float *rr = R + (long long)q * C * O + o;
     const float *ri = rr + (long long)Q * C * O;
+    const float *u = U + (long long)b * C * 2 * Q + q;
+    float vr = 0.f, vi = 0.f;
     for (int c = 0; c < C; ++c) {
       const float ur = u[(long long)c * 2 * Q], ui = u[(long long)c * 2 * Q + Q];
       const float ar = rr[c * O], ai = ri[c * O];
@@ -278,18 +280,20 @@ __global__ void k_mix(const float *__restrict__ U, const float *__restrict__ R,
 
 //   dU[b][c][q] = sum_o conj-transpose action:  dUr = sum (Rr dVr + Ri dVi),
 //   dUi = sum (Rr dVi - Ri dVr)
+// One thread per (b, q, c), c fastest: each lane walks its own row R[q][c][.]
+// (one cache line) and dV[b][.][q] is a broadcast per mode.
 __global__ void k_mix_bwd_data(const float *__restrict__ dV, const float *__restrict__ R,
                                float *__restrict__ dU, int B, int C, int O, int Q) {
   const long long total = (long long)B * C * Q;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const int q = (int)(t % Q);
-    const int c = (int)((t / Q) % C);
-    const int b = (int)(t / ((long long)Q * C));
-    float gr = 0.f, gi = 0.f;
-    const float *dv = dV + (long long)b * O * 2 * Q + q;
+    const int c = (int)(t % C);
+    const int q = (int)((t / C) % Q);
+    const int b = (int)(t / ((long long)C * Q));
     const float *rr = R + ((long long)q * C + c) * O;
     const float *ri = rr + (long long)Q * C * O;
+    const float *dv = dV + (long long)b * O * 2 * Q + q;
+    float gr = 0.f, gi = 0.f;
     for (int o = 0; o < O; ++o) {
       const float vr = dv[(long long)o * 2 * Q], vi = dv[(long long)o * 2 * Q + Q];
       gr += rr[o] * vr + ri[o] * vi;
