@@ -326,24 +326,103 @@ __global__ void k_mix_bwd_weight(const float *__restrict__ U, const float *__res
   }
 }
 
-// out[m] = sum_r in[r * M + m]  (fixed order: deterministic)
-// out[m] = sum over r of in[r][m].  A block owns 64 consecutive m; its 16
-// thread rows take every 16th r, and the 16 partial sums are added in a
-// fixed order, so the result does not depend on scheduling.
-constexpr int kSumCols = 64, kSumRows = 16;
+// LDS versions of the two mixing gradients, one block per mode q: the block
+// gathers the mode's strided spectra once into LDS (and, for the data
+// gradient, the mode's weight rows), so every global load of the inner loops
+// becomes an LDS read.  Same sums in the same order as the kernels above.
+constexpr int kMixThreads = 256;
+
+__global__ void __launch_bounds__(kMixThreads)
+    k_mix_bwd_data_lds(const float *__restrict__ dV, const float *__restrict__ R,
+                       float *__restrict__ dU, int B, int C, int O, int Q) {
+  extern __shared__ float sm[];
+  const int q = blockIdx.x;
+  const int OP = O + 1;                       // padded row: lanes of one o hit distinct banks
+  float *rre = sm, *rim = sm + C * OP;        // [C][O + 1]
+  float *vre = sm + 2 * C * OP, *vim = vre + B * O;  // [B][O]
+  const float *Rq = R + (long long)q * C * O;
+  const long long QCO = (long long)Q * C * O;
+  for (int e = threadIdx.x; e < C * O; e += kMixThreads) {
+    const int c = e / O, o = e % O;
+    rre[c * OP + o] = Rq[e];
+    rim[c * OP + o] = Rq[QCO + e];
+  }
+  for (int e = threadIdx.x; e < B * O; e += kMixThreads) {
+    const float *dv = dV + (long long)e * 2 * Q + q;  // e = b * O + o
+    vre[e] = dv[0];
+    vim[e] = dv[Q];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < B * C; e += kMixThreads) {
+    const int b = e / C, c = e % C;
+    const float *rr = rre + c * OP, *ri = rim + c * OP;
+    const float *vr_ = vre + b * O, *vi_ = vim + b * O;
+    float gr = 0.f, gi = 0.f;
+    for (int o = 0; o < O; ++o) {
+      const float vr = vr_[o], vi = vi_[o];
+      gr += rr[o] * vr + ri[o] * vi;
+      gi += rr[o] * vi - ri[o] * vr;
+    }
+    float *du = dU + ((long long)b * C + c) * 2 * Q + q;
+    du[0] = gr;
+    du[Q] = gi;
+  }
+}
+
+__global__ void __launch_bounds__(kMixThreads)
+    k_mix_bwd_weight_lds(const float *__restrict__ U, const float *__restrict__ dV,
+                         float *__restrict__ dR, int B, int C, int O, int Q) {
+  extern __shared__ float sm[];
+  const int q = blockIdx.x;
+  float *ure = sm, *uim = sm + B * C;            // [B][C]
+  float *vre = sm + 2 * B * C, *vim = vre + B * O;  // [B][O]
+  for (int e = threadIdx.x; e < B * C; e += kMixThreads) {
+    const float *u = U + (long long)e * 2 * Q + q;  // e = b * C + c
+    ure[e] = u[0];
+    uim[e] = u[Q];
+  }
+  for (int e = threadIdx.x; e < B * O; e += kMixThreads) {
+    const float *v = dV + (long long)e * 2 * Q + q;
+    vre[e] = v[0];
+    vim[e] = v[Q];
+  }
+  __syncthreads();
+  const long long QCO = (long long)Q * C * O;
+  for (int e = threadIdx.x; e < C * O; e += kMixThreads) {
+    const int c = e / O, o = e % O;
+    float gr = 0.f, gi = 0.f;
+    for (int b = 0; b < B; ++b) {
+      const float ur = ure[b * C + c], ui = uim[b * C + c];
+      const float vr = vre[b * O + o], vi = vim[b * O + o];
+      gr += ur * vr + ui * vi;
+      gi += ur * vi - ui * vr;
+    }
+    const long long t = (long long)q * C * O + e;
+    dR[t] = gr;
+    dR[t + QCO] = gi;
+  }
+}
+
+// out[m] = sum over r of in[r][m], in a fixed order (deterministic).  Block
+// (x, g) owns 64 consecutive m and the rows [g * rows, (g + 1) * rows); its 16
+// thread rows take every 16th of them and the 16 partial sums are added in a
+// fixed order.  With more than one row group the group sums go to tmp and a
+// second launch of the same kernel adds them.
+constexpr int kSumCols = 64, kSumRows = 16, kSumGroups = 64;
 __global__ void __launch_bounds__(kSumCols * kSumRows)
-    k_sum_rows(const float *__restrict__ in, float *__restrict__ out, int R, int M) {
+    k_sum_rows(const float *__restrict__ in, float *__restrict__ out, int R, int M, int rows) {
   __shared__ float part[kSumRows][kSumCols];
   const int m = blockIdx.x * kSumCols + threadIdx.x;
+  const int r0 = blockIdx.y * rows, r1 = min(R, r0 + rows);
   float acc = 0.f;
   if (m < M)
-    for (int r = threadIdx.y; r < R; r += kSumRows) acc += in[(long long)r * M + m];
+    for (int r = r0 + threadIdx.y; r < r1; r += kSumRows) acc += in[(long long)r * M + m];
   part[threadIdx.y][threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.y == 0 && m < M) {
     float s = 0.f;
     for (int q = 0; q < kSumRows; ++q) s += part[q][threadIdx.x];
-    out[m] = s;
+    out[(long long)blockIdx.y * M + m] = s;
   }
 }
 
@@ -370,13 +449,22 @@ __global__ void __launch_bounds__(kLossThreads)
   if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-__global__ void k_loss_final(const float *__restrict__ partial, int n, float inv_count,
-                             float *__restrict__ loss) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    float acc = 0.f;
-    for (int i = 0; i < n; ++i) acc += partial[i];
-    *loss = acc * inv_count;
+// Sum of the per-block partials: each thread adds a strided share in a fixed
+// order, then a fixed pairwise tree in LDS (deterministic).
+constexpr int kLossFinal = 256;
+__global__ void __launch_bounds__(kLossFinal)
+    k_loss_final(const float *__restrict__ partial, int n, float inv_count,
+                 float *__restrict__ loss) {
+  __shared__ float sh[kLossFinal];
+  float acc = 0.f;
+  for (int i = threadIdx.x; i < n; i += kLossFinal) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kLossFinal / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *loss = sh[0] * inv_count;
 }
 
 // Adam with bias correction folded into lr_t = lr sqrt(1 - b2^t) / (1 - b1^t).
@@ -437,15 +525,40 @@ hipError_t launch_mix(const float *U, const float *R, float *V, int B, int C, in
 }
 hipError_t launch_mix_bwd(const float *U, const float *dV, const float *R, float *dU, float *dR,
                           int B, int C, int O, int Q, hipStream_t s) {
-  hipLaunchKernelGGL(k_mix_bwd_data, dim3(grid_for((long long)B * C * Q)), dim3(256), 0, s, dV, R,
-                     dU, B, C, O, Q);
-  hipLaunchKernelGGL(k_mix_bwd_weight, dim3(grid_for((long long)Q * C * O)), dim3(256), 0, s, U,
-                     dV, dR, B, C, O, Q);
+  const size_t lds_data = (size_t)(2 * C * (O + 1) + 2 * B * O) * sizeof(float);
+  const size_t lds_weight = (size_t)(2 * B * C + 2 * B * O) * sizeof(float);
+  constexpr size_t kLdsMax = 48 * 1024;
+  if (lds_data <= kLdsMax)
+    hipLaunchKernelGGL(k_mix_bwd_data_lds, dim3(Q), dim3(kMixThreads), lds_data, s, dV, R, dU, B, C,
+                       O, Q);
+  else
+    hipLaunchKernelGGL(k_mix_bwd_data, dim3(grid_for((long long)B * C * Q)), dim3(256), 0, s, dV, R,
+                       dU, B, C, O, Q);
+  if (lds_weight <= kLdsMax)
+    hipLaunchKernelGGL(k_mix_bwd_weight_lds, dim3(Q), dim3(kMixThreads), lds_weight, s, U, dV, dR,
+                       B, C, O, Q);
+  else
+    hipLaunchKernelGGL(k_mix_bwd_weight, dim3(grid_for((long long)Q * C * O)), dim3(256), 0, s, U,
+                       dV, dR, B, C, O, Q);
   return hipGetLastError();
 }
-hipError_t launch_sum_rows(const float *in, float *out, int R, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_rows, dim3((M + kSumCols - 1) / kSumCols), dim3(kSumCols, kSumRows), 0, s,
-                     in, out, R, M);
+// Row groups: enough blocks to spread over the chip (about 512), at most
+// kSumGroups groups, so tmp needs kSumGroups * M floats.
+int sum_rows_groups() { return kSumGroups; }
+hipError_t launch_sum_rows(const float *in, float *out, int R, int M, float *tmp, hipStream_t s) {
+  if (R <= 0 || M <= 0) return hipSuccess;
+  const int cb = (M + kSumCols - 1) / kSumCols;
+  int g = 512 / cb;
+  g = g < 1 ? 1 : (g > kSumGroups ? kSumGroups : g);
+  if (g > R) g = R;
+  const int rows = (R + g - 1) / g;
+  g = (R + rows - 1) / rows;
+  if (g == 1) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(cb, 1), dim3(kSumCols, kSumRows), 0, s, in, out, R, M, R);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_sum_rows, dim3(cb, g), dim3(kSumCols, kSumRows), 0, s, in, tmp, R, M, rows);
+  hipLaunchKernelGGL(k_sum_rows, dim3(cb, 1), dim3(kSumCols, kSumRows), 0, s, tmp, out, g, M, g);
   return hipGetLastError();
 }
 constexpr int kLossBlocks = 1024;
@@ -455,7 +568,7 @@ hipError_t launch_loss(const float *y, const float *t, float *dy, float *partial
   const float inv = 1.f / (float)n;
   hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(kLossThreads), 0, s, y, t, dy, partial, n, inv,
                      focus);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, partial, kLossBlocks, inv, loss);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kLossFinal), 0, s, partial, kLossBlocks, inv, loss);
   return hipGetLastError();
 }
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, long long n, float lr_t,

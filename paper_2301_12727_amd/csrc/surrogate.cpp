@@ -39,7 +39,8 @@ hipError_t launch_mix(const float *U, const float *R, float *V, int B, int C, in
                       hipStream_t s);
 hipError_t launch_mix_bwd(const float *U, const float *dV, const float *R, float *dU, float *dR,
                           int B, int C, int O, int Q, hipStream_t s);
-hipError_t launch_sum_rows(const float *in, float *out, int R, int M, hipStream_t s);
+hipError_t launch_sum_rows(const float *in, float *out, int R, int M, float *tmp, hipStream_t s);
+int sum_rows_groups();
 int loss_partials();
 hipError_t launch_loss(const float *y, const float *t, float *dy, float *partial, float *loss,
                        float focus, long long n, hipStream_t s);
@@ -84,7 +85,7 @@ namespace {
 // Workspace layout for a batch (offsets in floats).
 struct Layout {
   size_t mats, ones, h, z, U, T1, T2, V, I1, I2, y, dy, lossp, loss, dh, dh2, dz, dV, dU, part,
-      bpart, total;
+      bpart, red, total;
   long long Kc, S;  // split-K chunk and chunk count (Kc * S = n^3)
 };
 
@@ -123,6 +124,7 @@ Layout layout(const bbsur_model *m, int B) {
   const size_t mw = (size_t)std::max(m->W, m->cin);
   o.part = take((size_t)B * o.S * mw * mw);
   o.bpart = take((size_t)B * o.S * mw);
+  o.red = take((size_t)sum_rows_groups() * mw * mw);  // row-group sums of a gradient
   o.total = a;
   return o;
 }
@@ -286,7 +288,8 @@ int weight_grad(const Ctx &c, const float *D, const float *H, int M, int N, floa
                    (long long)M * N, N, 1);
     if (rc) return rc;
   }
-  return hipchk(launch_sum_rows(part, grad, (int)(c.B * c.o.S), M * N, c.s), "grad sum");
+  return hipchk(launch_sum_rows(part, grad, (int)(c.B * c.o.S), M * N, c.ws + c.o.red, c.s),
+                "grad sum");
 }
 
 // grad (M) = sum_b sum_p D[b][m][p]
@@ -299,7 +302,8 @@ int bias_grad(const Ctx &c, const float *D, int M, float *grad) {
                    c.ws + c.o.ones, 0, 1, 0, bpart + (size_t)b * c.o.S * M, M, 1, 0);
     if (rc) return rc;
   }
-  return hipchk(launch_sum_rows(bpart, grad, (int)(c.B * c.o.S), M, c.s), "bias sum");
+  return hipchk(launch_sum_rows(bpart, grad, (int)(c.B * c.o.S), M, c.ws + c.o.red, c.s),
+                "bias sum");
 }
 
 int prepare(const bbsur_model *cm, void *ws, uint64_t bytes, int B, hipStream_t s, Ctx *c) {

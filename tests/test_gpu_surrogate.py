@@ -89,18 +89,28 @@ def test_forward_matches_fp64_reference():
     assert err < 2e-2
 
 
-def test_gradients_match_fp64_reference():
-    p, x = _setup(2, 2)
+# The wide configuration's per-mode weights (80 x 80) are too large for the
+# LDS mixing-gradient kernels and take the global-memory ones; its weight
+# gradients have 6400 columns, so their row sums use several row groups.
+WIDE = nn_ref.Config(n=8, cin=4, width=80, layers=1, mx=2, my=2, mz=2)
+
+
+@pytest.mark.parametrize("cfg", [CFG, WIDE], ids=["narrow", "wide"])
+def test_gradients_match_fp64_reference(cfg):
+    rng = np.random.default_rng(2)
+    p = nn_ref.init_params(cfg, 2).astype(np.float32)
+    p += rng.normal(0, 0.02, p.shape).astype(np.float32)
+    x = rng.normal(0, 1, (2, cfg.cin) + (cfg.n,) * 3).astype(np.float32)
     rng = np.random.default_rng(3)
-    dy = rng.normal(0, 1, (2, 1) + (CFG.n,) * 3).astype(np.float32)
-    model = sg.Surrogate(**CFG.__dict__)
+    dy = rng.normal(0, 1, (2, 1) + (cfg.n,) * 3).astype(np.float32)
+    model = sg.Surrogate(**cfg.__dict__)
     g = model.backward(torch.from_numpy(p).cuda(), torch.from_numpy(x).cuda(),
                        torch.from_numpy(dy).cuda()).cpu().numpy()
     gref, _, _ = nn_ref.backward(p.astype(np.float64), x.astype(np.float64),
-                                 dy.astype(np.float64), CFG)
+                                 dy.astype(np.float64), cfg)
     errs = {}
     off = 0
-    for name, shape in nn_ref.param_layout(CFG):
+    for name, shape in nn_ref.param_layout(cfg):
         n = int(np.prod(shape))
         errs[name] = rel(g[off:off + n], gref[off:off + n])
         off += n
