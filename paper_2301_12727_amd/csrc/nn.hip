@@ -1,10 +1,12 @@
 // Kernels of the learned surrogate: a generic batched strided GEMM on the
 // gfx950 BF16 matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation) and
-// the element-wise pieces of a Fourier neural operator (GELU and its
-// gradient, per-mode complex channel mixing, loss, Adam).
+// the element-wise pieces of a Fourier neural operator (GELU gradient,
+// per-mode complex channel mixing, loss, Adam; GELU itself is applied in the
+// GEMM epilogue).
 //
 // GEMM: C[b](m, n) = alpha * sum_k A[b](m, k) * B[b](k, n) + beta * C[b](m, n)
-// (+ bias[m]).  Operands are FP32 in memory, rounded to BF16 when staged into
+// (+ bias[m]); optionally GELU(C) into a second output as well, or, for the
+// backward pass, C * GELU'(z) into the second output in place of C.  Operands are FP32 in memory, rounded to BF16 when staged into
 // LDS ("FP32 in, BF16 MFMA, FP32 accumulate").  Element addresses are fully
 // strided, and K may be split into two segments held at different offsets
 // (k >= seg_k reads from base + seg_off), which lets the real and imaginary
@@ -18,6 +20,12 @@ namespace bbsur {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) +
+         z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
 
 constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
 constexpr int kThreads = 256;
@@ -204,7 +212,18 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
       if (g.bias) {
         v.x += g.bias[gm]; v.y += g.bias[gm + 1]; v.z += g.bias[gm + 2]; v.w += g.bias[gm + 3];
       }
+      const long long go = (long long)b * g.sCb + (long long)gn * g.sCn + gm;
+      if (g.gelu_z) {
+        const float4 zz = *reinterpret_cast<const float4 *>(g.gelu_z + go);
+        *reinterpret_cast<float4 *>(g.gelu_out + go) =
+            make_float4(v.x * gelu_grad(zz.x), v.y * gelu_grad(zz.y), v.z * gelu_grad(zz.z),
+                        v.w * gelu_grad(zz.w));
+        continue;
+      }
       *dst = v;
+      if (g.gelu_out)
+        *reinterpret_cast<float4 *>(g.gelu_out + go) =
+            make_float4(gelu(v.x), gelu(v.y), gelu(v.z), gelu(v.w));
     }
     return;
   }
@@ -217,24 +236,19 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
     float v = g.alpha * acc[r];
     if (g.beta != 0.f) v += g.beta * *c;
     if (g.bias) v += g.bias[row];
+    const long long go = (long long)b * g.sCb + (long long)row * g.sCm + (long long)col * g.sCn;
+    if (g.gelu_z) {
+      g.gelu_out[go] = v * gelu_grad(g.gelu_z[go]);
+      continue;
+    }
     *c = v;
+    if (g.gelu_out) g.gelu_out[go] = gelu(v);
   }
 }
 
 // ---------------------------------------------------------------- element-wise
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
 
-__device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.f + erff(z * 0.70710678118654752f)) +
-         z * expf(-0.5f * z * z) * 0.39894228040143268f;
-}
-
-__global__ void k_gelu(const float *__restrict__ z, float *__restrict__ h, long long n) {
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
-       t += (long long)gridDim.x * blockDim.x)
-    h[t] = gelu(z[t]);
-}
 
 __global__ void k_gelu_bwd(const float *__restrict__ z, const float *__restrict__ dh,
                            float *__restrict__ dz, long long n) {
@@ -506,10 +520,6 @@ static unsigned grid_for(long long n) {
   return (unsigned)(b > 16384 ? 16384 : (b < 1 ? 1 : b));
 }
 
-hipError_t launch_gelu(const float *z, float *h, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_gelu, dim3(grid_for(n)), dim3(256), 0, s, z, h, n);
-  return hipGetLastError();
-}
 hipError_t launch_gelu_bwd(const float *z, const float *dh, float *dz, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(n)), dim3(256), 0, s, z, dh, dz, n);
   return hipGetLastError();
@@ -588,7 +598,8 @@ static bool al4(long long v) { return v % 4 == 0; }
 // Picks the staging modes: float4 loads along an operand's unit-stride axis
 // when that axis' extent, the other strides, the segment offset and the base
 // are all multiples of four floats; the column-major epilogue when C is
-// unit-stride along m under the same conditions.
+// unit-stride along m under the same conditions (and gelu_out, if any, 16-byte
+// aligned).
 hipError_t launch_gemm(const GemmArgs &g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return hipSuccess;
   GemmArgs g = g0;
@@ -602,7 +613,8 @@ hipError_t launch_gemm(const GemmArgs &g0, hipStream_t s) {
   if (b16 && g.sBn == 1 && al4(g.N) && al4(g.sBk)) bm = 1;
   else if (b16 && g.sBk == 1 && al4(g.K) && al4(g.sBn)) bm = 2;
   g.c_mfast = (g.sCm == 1 && g.sCn != 1 && al4(g.M) && al4(g.sCn) && al4(g.sCb) &&
-               (uintptr_t)g.C % 16 == 0) ? 1 : 0;
+               (uintptr_t)g.C % 16 == 0 && (uintptr_t)g.gelu_out % 16 == 0 &&
+               (uintptr_t)g.gelu_z % 16 == 0) ? 1 : 0;
   dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, g.batch);
   dim3 blk(kThreads);
 #define BBSUR_GEMM(AM, BM) hipLaunchKernelGGL((k_gemm<AM, BM>), grid, blk, 0, s, g)

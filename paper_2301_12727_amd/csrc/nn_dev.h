@@ -21,6 +21,9 @@ struct GemmArgs {
   int a_kfast, b_nfast;  // which axis is unit-stride (staging order of the scalar path)
   int c_mfast;           // set by the launcher: column-major epilogue
   float alpha, beta;
+  float *gelu_out;       // optional second output, with C's strides: GELU(C(m, n)), or
+                         // with gelu_z set C(m, n) * GELU'(gelu_z(m, n)) instead of C
+  const float *gelu_z;
 };
 
 }  // namespace bbsur

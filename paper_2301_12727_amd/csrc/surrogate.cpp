@@ -32,7 +32,6 @@ int set_error(int code, const char *msg);
 
 namespace bbsur {
 hipError_t launch_gemm(const GemmArgs &g, hipStream_t s);
-hipError_t launch_gelu(const float *z, float *h, long long n, hipStream_t s);
 hipError_t launch_gelu_bwd(const float *z, const float *dh, float *dz, long long n, hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
 hipError_t launch_mix(const float *U, const float *R, float *V, int B, int C, int O, int Q,
@@ -211,7 +210,8 @@ struct G {
   int run(int batch, int M, int N, int K, const float *A, long long sAb, long long sAm,
           long long sAk, int aseg, long long asegoff, const float *B, long long sBb, long long sBk,
           long long sBn, float *C, long long sCb, long long sCm, long long sCn, float beta = 0.f,
-          const float *bias = nullptr) const {
+          const float *bias = nullptr, float *gelu_out = nullptr,
+          const float *gelu_z = nullptr) const {
     GemmArgs g{};
     g.A = A; g.B = B; g.C = C; g.bias = bias;
     g.M = M; g.N = N; g.K = K; g.batch = batch;
@@ -222,6 +222,8 @@ struct G {
     g.b_nfast = (sBn == 1) ? 1 : 0;
     g.alpha = 1.f;
     g.beta = beta;
+    g.gelu_out = gelu_out;
+    g.gelu_z = gelu_z;
     return hipchk(launch_gemm(g, s), "gemm");
   }
 };
@@ -257,8 +259,11 @@ int spectral_forward(const Ctx &c, const float *in, float *out, size_t fx, int n
 
 // Inverse transform of spectra `in` ([nb][2][Q]) onto volumes `out`
 // ([nb][n^3], accumulated when beta = 1); gx selects the weighted (forward
-// pass) or unweighted (gradient) x matrix.
-int spectral_inverse(const Ctx &c, const float *in, float *out, size_t gx, int nb, float beta) {
+// pass) or unweighted (gradient) x matrix.  With act != NULL the last stage
+// also stores GELU of the result there (same layout); with zpre != NULL as
+// well it stores result * GELU'(zpre) there instead of the result.
+int spectral_inverse(const Ctx &c, const float *in, float *out, size_t gx, int nb, float beta,
+                     float *act = nullptr, const float *zpre = nullptr) {
   const bbsur_model *m = c.m;
   const int n = m->n, mx = m->mx, my = m->my, mz = m->mz;
   const long long n2 = m->n2;
@@ -273,7 +278,7 @@ int spectral_inverse(const Ctx &c, const float *in, float *out, size_t gx, int n
                (long long)n * 2 * mz);
   if (!rc)
     rc = g.run(nb, (int)n2, n, 4 * mz, I2, 2LL * n * n * 2 * mz, 2 * mz, 1, 2 * mz,
-               n2 * 2 * mz, c.mat(m->o_gz), 0, n, 1, out, m->P, 1, n2, beta);
+               n2 * 2 * mz, c.mat(m->o_gz), 0, n, 1, out, m->P, 1, n2, beta, nullptr, act, zpre);
   return rc;
 }
 
@@ -352,8 +357,8 @@ int forward(const Ctx &c, const float *prm, const float *x) {
     if (!rc) rc = spectral_forward(c, hin, Ul, m->o_fx, B * W);
     if (!rc)
       rc = hipchk(launch_mix(Ul, prm + m->p_r[l], c.ws + c.o.V, B, W, W, (int)m->Q, c.s), "mix");
-    if (!rc) rc = spectral_inverse(c, c.ws + c.o.V, zl, m->o_gx, B * W, 1.f);
-    if (!rc) rc = hipchk(launch_gelu(zl, h + (l + 1) * BWP, BWP, c.s), "gelu");
+    // z_l accumulates the inverse transform; h_{l+1} = GELU(z_l) in the same epilogue
+    if (!rc) rc = spectral_inverse(c, c.ws + c.o.V, zl, m->o_gx, B * W, 1.f, h + (l + 1) * BWP);
   }
   if (!rc)
     rc = g.run(B, 1, (int)m->P, W, prm + m->p_pw, 0, W, 1, 0, 0, h + m->L * BWP,
@@ -377,7 +382,9 @@ int backward(const Ctx &c, const float *prm, const float *x, const float *dy, fl
   for (int l = m->L - 1; !rc && l >= 0; --l) {
     const float *hin = h + l * BWP, *zl = z + l * BWP;
     const float *Ul = U + (size_t)l * B * W * 2 * m->Q;
-    rc = hipchk(launch_gelu_bwd(zl, dh, dz, BWP, c.s), "gelu grad");
+    // dz = dh * GELU'(z_l): for the top layer here, below it in the epilogue of
+    // the previous iteration's last inverse-transform stage
+    if (l == m->L - 1) rc = hipchk(launch_gelu_bwd(zl, dh, dz, BWP, c.s), "gelu grad");
     if (!rc) rc = weight_grad(c, dz, hin, W, W, grad + m->p_w[l]);
     if (!rc) rc = bias_grad(c, dz, W, grad + m->p_b[l]);
     if (!rc)
@@ -387,7 +394,12 @@ int backward(const Ctx &c, const float *prm, const float *x, const float *dy, fl
     if (!rc)
       rc = hipchk(launch_mix_bwd(Ul, c.ws + c.o.dV, prm + m->p_r[l], c.ws + c.o.dU,
                                  grad + m->p_r[l], B, W, W, (int)m->Q, c.s), "mix grad");
-    if (!rc) rc = spectral_inverse(c, c.ws + c.o.dU, dh2, m->o_gxu, B * W, 1.f);
+    // dh2 = dL/dh_l; below the bottom layer h_l = GELU(z_{l-1}), so the next
+    // iteration's dz is formed here (dz_l is no longer read)
+    if (!rc && l > 0)
+      rc = spectral_inverse(c, c.ws + c.o.dU, dh2, m->o_gxu, B * W, 1.f, dz, z + (l - 1) * BWP);
+    else if (!rc)
+      rc = spectral_inverse(c, c.ws + c.o.dU, dh2, m->o_gxu, B * W, 1.f);
     std::swap(dh, dh2);
   }
   if (!rc) rc = weight_grad(c, dh, x, W, m->cin, grad + m->p_lw);
