@@ -329,7 +329,13 @@ def main():
     ms = plan.solve_profiled(mat, src, peak, ws)
     pidx2, _ = plan.status(ws)
     assert pidx2 == pidx
-    ab = algorithmic_bytes(case, info, plan.segment_classes(ws))
+    classes = plan.segment_classes(ws)
+    ab = algorithmic_bytes(case, info, classes)
+    # the byte model's tile kinds must be the library's own
+    kinds = tile_kinds(case, info, classes)
+    counts = plan.tile_counts(ws)
+    if counts != tuple(int((kinds == k).sum()) for k in (1, 0, 2)):
+        raise RuntimeError(f"byte model tile kinds disagree with the library: {counts}")
     avg = {k: m / case.n_steps for k, m in zip(KERNELS, ms)}
     dom = max(KERNELS, key=lambda k: avg[k])
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
@@ -348,7 +354,8 @@ def main():
             "bytes_per_cell_update": round(ab["per_cell_update"], 2),
             "acoustic_cell_fraction": round(ab["acoustic_fraction"], 4),
             "acoustic_tile_cell_fraction": round(ab["acoustic_tile_fraction"], 4),
-            "deep_tile_cell_fraction": round(ab["deep_tile_fraction"], 4)}
+            "deep_tile_cell_fraction": round(ab["deep_tile_fraction"], 4),
+            "tiles_acoustic_general_deep": list(counts)}
 
     out = {
         "metric": "Gcell-updates/s",

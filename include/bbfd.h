@@ -152,9 +152,10 @@ int bbfd_solve_direct(const bbfd_plan *plan, const uint8_t *mat, const float *sr
    [4].  A tile (64 x tile_rows x tile_planes cells, see bbfd_plan_info) is
    acoustic when every one of its row segments is of a lossless-fluid class
    (bbfd_segment_classes) on every plane, and deep when moreover it lies, with
-   3 cells around it, inside the grid and outside the absorbing layer and all
-   of those cells hold one fluid; such tiles run kernels specialised to those
-   cases.  Results are identical to bbfd_solve. */
+   3 cells around it, inside the grid and outside the absorbing layer, all of
+   those cells hold one fluid and no elastic segment within two rows or planes
+   reads its sigma_yy or sigma_zz; such tiles run kernels specialised to those
+   cases (bbfd_tile_counts).  Results are identical to bbfd_solve. */
 int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
                         float *peak, void *workspace, uint64_t workspace_bytes, void *stream,
                         double *ms_out);
@@ -178,6 +179,13 @@ int bbfd_status(const bbfd_plan *plan, const void *workspace, int64_t *peak_inde
    n is its size (BBFD_EINVAL if smaller).  Synchronises stream. */
 int bbfd_segment_classes(const bbfd_plan *plan, const void *workspace, uint8_t *classes,
                          uint64_t n, void *stream);
+
+/* Diagnostic: the number of tiles of each kind in the last solve in this
+   workspace, counts (host, 3 values): acoustic tiles run by the acoustic
+   velocity and stress kernels [0], general tiles [1], deep tiles run by the
+   fused step [2] (tile kinds as described at bbfd_solve_profiled; their sum is
+   the plan's tile count).  Synchronises stream. */
+int bbfd_tile_counts(const bbfd_plan *plan, const void *workspace, int32_t *counts, void *stream);
 
 /* ---- Batched sweeps: many independent solves of uneven size in one launch.
    Each problem keeps its own grid, frequency, time step, tables and step count.

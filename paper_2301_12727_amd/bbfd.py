@@ -54,7 +54,7 @@ class PlanInfo(C.Structure):
 EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_material_constants", "bbfd_transducer_elements", "bbfd_source_rayleigh",
            "bbfd_solve", "bbfd_solve_direct", "bbfd_solve_profiled", "bbfd_status",
-           "bbfd_segment_classes",
+           "bbfd_segment_classes", "bbfd_tile_counts",
            "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
            "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
            "bbfd_batch_status", "bbfd_batch_autotune"]
@@ -84,6 +84,7 @@ def lib():
         L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
         L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
         L.bbfd_segment_classes.argtypes = [vp, vp, vp, C.c_uint64, vp]
+        L.bbfd_tile_counts.argtypes = [vp, vp, vp, vp]
         L.bbfd_last_error.restype = C.c_char_p
         L.bbfd_batch_create.argtypes = [C.POINTER(Problem), C.c_int32, C.POINTER(vp)]
         L.bbfd_batch_destroy.argtypes = [vp]
@@ -223,6 +224,13 @@ class Plan:
         _check(lib().bbfd_status(self.h, C.c_void_p(ws.data_ptr()), C.byref(idx), C.byref(val),
                                  C.c_void_p(_stream(stream))))
         return int(idx.value), float(val.value)
+
+    def tile_counts(self, ws, stream=None):
+        """Tiles of each kind in the last solve in ws: (acoustic, general, deep)."""
+        out = (C.c_int32 * 3)()
+        _check(lib().bbfd_tile_counts(self.h, C.c_void_p(ws.data_ptr()), out,
+                                      C.c_void_p(_stream(stream))))
+        return tuple(out)
 
     def segment_classes(self, ws, stream=None):
         """Row-segment classes of the last solve in ws, uint8 [nz][ny][ceil(nx/64)]

@@ -115,6 +115,8 @@ struct bbfd_plan {
          off_cls = 0, off_keep = 0, off_alt = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
          ws_bytes = 0;
   int n_tiles = 0;
+  bool deep = false;    // some tile can be deep: the fused step is launched
+  bool branch = false;  // the captured steps run as two branches
   std::mutex mu;
   hipStream_t cap_stream = nullptr;
   hipStream_t side_stream = nullptr;  // second branch of the captured steps
@@ -257,6 +259,9 @@ int build_tables(bbfd_plan *pl) {
   return BBFD_OK;
 }
 
+// Tiles from which a single solve's captured steps run as two branches.
+constexpr int kBranchTiles = 2048;
+
 void layout(bbfd_plan *pl) {
   const bbfd_problem &p = pl->prob;
   Grid &g = pl->g;
@@ -284,6 +289,18 @@ void layout(bbfd_plan *pl) {
   pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->off_keep = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->n_tiles = pl->nseg * (int)((p.ny + kRows - 1) / kRows) * ((p.nz + pl->kchunk - 1) / pl->kchunk);
+  // A deep tile needs a whole x segment, a row block and a z chunk with
+  // kDeepReach cells around them inside the grid and outside the layer; where
+  // no tile can be deep the fused step is not launched at all.
+  auto fits = [&](int n, int len) {
+    for (int a = 0; a < n; a += len)
+      if (a + len <= n && a - kDeepReach >= p.pml && a + len - 1 + kDeepReach < n - p.pml) return true;
+    return false;
+  };
+  pl->deep = fits(p.nx, kSeg) && fits(p.ny, kRows) && fits(p.nz, pl->kchunk);
+  // Side-by-side branches fill the tails of launches that take many rounds of
+  // blocks; small grids are bound by launch and dependency latency instead.
+  pl->branch = pl->n_tiles >= kBranchTiles;
   pl->off_kind = o; o += round_up((size_t)pl->n_tiles, 256);
   pl->off_lists = o; o += round_up(3 * (size_t)pl->n_tiles * sizeof(int), 256);
   pl->off_counts = o; o += 256;
@@ -450,7 +467,7 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
     }
     if (side) {
       if ((e = link(s, side, pl->fork)) != hipSuccess ||
-          (e = launch_deep(ad, lists, counts, side)) != hipSuccess ||
+          (pl->deep && (e = launch_deep(ad, lists, counts, side)) != hipSuccess) ||
           (e = launch_velocity(av, lists, counts, 0, s)) != hipSuccess ||
           (e = launch_velocity(av, lists, counts, 1, s)) != hipSuccess ||
           (e = link(side, s, pl->join)) != hipSuccess ||
@@ -470,7 +487,7 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
       if (ev) (void)hipEventRecord(ev[2 * (kStepKernels * n + q)], s);
       if (q < 2) e = launch_velocity(av, lists, counts, q, s);
       else if (q < 4) e = launch_stress(as, lists, counts, q - 2, s);
-      else e = launch_deep(ad, lists, counts, s);
+      else if (pl->deep) e = launch_deep(ad, lists, counts, s);
       if (e != hipSuccess) return hip_fail(e, "step launch");
       if (ev) (void)hipEventRecord(ev[2 * (kStepKernels * n + q) + 1], s);
     }
@@ -751,7 +768,7 @@ int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float
     if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
       return hip_fail(e, "begin capture");
     rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, pl->cap_stream, nullptr,
-                       pl->side_stream);
+                       pl->branch ? pl->side_stream : nullptr);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(pl->cap_stream, &g);
     if (rc) {
@@ -783,6 +800,17 @@ int bbfd_status(const bbfd_plan *pl, const void *workspace, int64_t *peak_index,
   if (peak_value) *peak_value = st.peak_value;
   if (st.flags & kStatusIndex) return fail(BBFD_EINDEX, "material index >= n_materials in the map");
   if (st.flags & kStatusDiverged) return fail(BBFD_EDIVERGED, "non-finite peak pressure (diverged)");
+  return BBFD_OK;
+}
+
+int bbfd_tile_counts(const bbfd_plan *pl, const void *workspace, int32_t *counts, void *stream) {
+  if (!pl || !workspace || !counts) return fail(BBFD_EINVAL, "null argument");
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream sync");
+  int c[3] = {0, 0, 0};
+  e = hipMemcpy(c, (const char *)workspace + pl->off_counts, sizeof c, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "tile count read");
+  for (int q = 0; q < 3; ++q) counts[q] = c[q];
   return BBFD_OK;
 }
 

@@ -100,6 +100,8 @@ struct StepArgs {
 
 // Rows of a single-solve tile (one wave per row).
 constexpr int kRows = 4;
+// Cells around a deep tile that its fused velocity + stress step reads.
+constexpr int kDeepReach = 3;
 
 // Batched sweeps: one entry per (solve, tile); solves are ordered by
 // decreasing step count so the live tiles of step n are a prefix of the table.

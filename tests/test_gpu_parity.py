@@ -316,6 +316,20 @@ def test_deep_tiles_fused_step():
     peak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
     ms = plan.solve_profiled(mat_d, src, peak, ws)
     plan.status(ws)
-    say(f"[parity] deep tiles: kernel ms {[round(m, 3) for m in ms]}")
-    assert ms[4] > 0.0                     # the fused kernel did work
+    counts = plan.tile_counts(ws)
+    say(f"[parity] deep tiles: kernel ms {[round(m, 3) for m in ms]}, tiles {counts}")
+    # the benchmark's byte model classifies tiles the same way as the library
+    import bench
+    kinds = bench.tile_kinds(case, plan.info, plan.segment_classes(ws))
+    assert counts[2] > 0 and sum(counts) == kinds.size
+    assert counts == tuple(int((kinds == k).sum()) for k in (1, 0, 2))
     assert np.array_equal(peak.cpu().numpy(), P)
+    # batched sweeps run the two-pass kernels in place: same map bit for bit
+    b = bb.Batch([case])
+    bws = b.workspace()
+    bsrc = torch.empty((case.ny, case.nx), dtype=torch.complex64, device="cuda")
+    b.source_rayleigh(0, case.transducer, bsrc, bws)
+    bpeak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    b.solve([mat_d], [bsrc], [bpeak], bws)
+    b.status(bws, 0)
+    assert np.array_equal(bpeak.cpu().numpy(), P)
