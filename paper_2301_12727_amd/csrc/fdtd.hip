@@ -267,15 +267,35 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
   ClassColumn col(A, j, bx, k0);
   uint32_t c = (uint32_t)g.off(i, j, k0);
   uint32_t qo = ((uint32_t)k0 * (uint32_t)(g.ny * g.nx) + (uint32_t)(j * g.nx + i)) * 4u;
+  // z windows of this column, one new plane loaded per step in z: v_z at
+  // planes k-2..k+1 (z0..z3), v_x and v_y at k-1..k+2 (x0..x3, y0..y3).  The
+  // velocities are not written by this kernel, so the window stays valid.
+  float z0, z1, z2, z3, x0, x1, x2, x3, y0, y1, y2, y3, zn = 0.f, xn = 0.f, yn = 0.f;
+  {
+    const uint32_t o = 4 * c;
+    z0 = ldb(vz, o - 2 * PL4); z1 = ldb(vz, o - PL4); z2 = ldb(vz, o); z3 = ldb(vz, o + PL4);
+    x0 = ldb(vx, o - PL4); x1 = ldb(vx, o); x2 = ldb(vx, o + PL4); x3 = ldb(vx, o + 2 * PL4);
+    y0 = ldb(vy, o - PL4); y1 = ldb(vy, o); y2 = ldb(vy, o + PL4); y3 = ldb(vy, o + 2 * PL4);
+  }
   for (int k = k0; k < k1; ++k, c += PL, qo += QL4) {
     const uint32_t o = 4 * c;
+    if (k != k0) {
+      z0 = z1; z1 = z2; z2 = z3; z3 = zn;
+      x0 = x1; x1 = x2; x2 = x3; x3 = xn;
+      y0 = y1; y1 = y2; y2 = y3; y3 = yn;
+    }
+    if (k + 1 < k1) {  // the next plane's new window entries
+      zn = ldb(vz, o + 2 * PL4);
+      xn = ldb(vx, o + 3 * PL4);
+      yn = ldb(vy, o + 3 * PL4);
+    }
     const bool pz = in_layer(k, g.nz, g.L);
     const int cl = col.at(k, k0);
     const float4 tz = pz ? A.pml.z[k] : make_float4(1.f, 0.f, 1.f, 0.f);
     const float pk = capture ? ldb_once(A.peak, qo) : 0.f;
     if (cl) {
       // acoustic path: only the (equal) normal stresses change
-      float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = DMB(vz, o, PL4);
+      float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = dbw(z0, z1, z2, z3);
       const float so = ldb_once(sxxp, o);
       const float q9 = px ? ldb_once(A.psi[9], o) : 0.f;
       const float q10 = py ? ldb_once(A.psi[10], o) : 0.f;
@@ -295,10 +315,10 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
     }
     const int m0 = ldi(idx, c), mx = ldi(idx, c + 1), my = ldi(idx, c + P), mz = ldi(idx, c + PL);
     const int mxy = ldi(idx, c + 1 + P), mxz = ldi(idx, c + 1 + PL), myz = ldi(idx, c + P + PL);
-    float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = DMB(vz, o, PL4);
+    float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = dbw(z0, z1, z2, z3);
     float dyvx = DPB(vx, o, P4), dxvy = DPB(vy, o, 4);
-    float dzvx = DPB(vx, o, PL4), dxvz = DPB(vz, o, 4);
-    float dzvy = DPB(vy, o, PL4), dyvz = DPB(vz, o, P4);
+    float dzvx = dfw(x0, x1, x2, x3), dxvz = DPB(vz, o, 4);
+    float dzvy = dfw(y0, y1, y2, y3), dyvz = DPB(vz, o, P4);
     float sxx = ldb_once(sxxp, o), syy = ldb_once(syyp, o), szz = ldb_once(szzp, o);
     float rxx = ldb_once(rxxp, o), ryy = ldb_once(ryyp, o), rzz = ldb_once(rzzp, o);
     float sxy = ldb_once(sxyp, o), sxz = ldb_once(sxzp, o), syz = ldb_once(syzp, o);
@@ -691,7 +711,7 @@ __global__ void __launch_bounds__(kSeg * kRows)
 // else 0.  Within that reach every other kernel's velocity update reduces to
 // the acoustic one (shear stresses of fluid edges are zero), so the fused
 // step's recomputed neighbours equal the values the neighbouring tiles store.
-constexpr int kReach = 3;
+constexpr int kReach = kDeepReach;
 __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
   const Grid &g = A.g;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A.n_tiles; t += gridDim.x * blockDim.x) {

@@ -4,8 +4,9 @@ Times the forward pass and the training step of the 3D FNO at its working size
 on synthetic inputs, and sets the forward pass against the HBM and matrix-core
 rooflines: the algorithmic bytes and FLOPs of every launch the forward pass
 issues are counted from the layer shapes (the contractions, the truncated
-transforms as three strided stages each way, the per-mode mixing, GELU), and
-divided by the measured time.  Prints one JSON line.
+transforms as three strided stages each way, the per-mode mixing; GELU is
+applied in the last inverse stage), and divided by the measured time.
+Prints one JSON line.
 
     python -m paper_2301_12727_amd.surrogate_bench [--batch 4] [--reps 20]
 """
@@ -43,8 +44,8 @@ def forward_counts(n, cin, W, L, mx, my, mz, B):
             ("mix", 2 * U + 2 * Q * W * W * f, 8 * Q * W * W * B),
             ("idft_x", U + I1, 2 * (4 * mz * my) * (2 * n) * (2 * mx) * nb),
             ("idft_y", I1 + I2, 2 * (n * 2 * mz) * (2 * n) * (4 * my) * nb),
-            ("idft_z", I2 + 2 * vol, 2 * n2 * n * (4 * mz) * nb),
-            ("gelu", 2 * vol, 0),
+            # last stage: reads I2 and z, writes z and GELU(z)
+            ("idft_z_gelu", I2 + 3 * vol, 2 * n2 * n * (4 * mz) * nb),
         ]
     rows.append(("project", vol + B * P * f, 2 * W * P * B))
     return rows
@@ -102,7 +103,7 @@ def main(argv=None):
                                 "achieved_tflops": round(tfl, 2),
                                 "bf16_frac": round(tfl / BF16_PEAK_TFLOPS, 5),
                                 "flop_per_byte": round(fflops / fbytes, 2)},
-           "forward_launches": {k: {"bytes": int(b), "flops": int(fl)} for k, b, fl in rows[:10]}}
+           "forward_launches": {k: {"bytes": int(b), "flops": int(fl)} for k, b, fl in rows[:9]}}
     print(json.dumps(out), flush=True)
 
 
