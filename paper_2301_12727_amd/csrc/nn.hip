@@ -45,22 +45,42 @@ __device__ __forceinline__ long long b_off(const GemmArgs &g, int k, int n) {
 // consecutive m (or n) per load.  Modes 1 and 2 need the vectorised axis'
 // extent, the other strides and the base 16-byte aligned (checked on the host,
 // see launch_gemm), so a float4 is either wholly inside the operand or wholly
-// outside it.  Every thread holds 8 values (two float4) of the next tile in
-// registers while the matrix cores work on the current one.
+// outside it.  Modes 3 and 4 are modes 1 and 2 for a BF16 operand: eight
+// values per 16-byte load, stored to LDS as they are (the FP32 modes round to
+// BF16 on the way in, so an operand kept in BF16 gives the same products).
+// Every thread holds 8 values of the next tile in registers while the matrix
+// cores work on the current one.
 struct Stage {
   float v[8];
+  uint4 raw;  // eight BF16 values (modes 3, 4)
 };
 
+__device__ __forceinline__ const float *fp(const void *p) { return static_cast<const float *>(p); }
+__device__ __forceinline__ const uint4 *bp(const void *p, long long off) {
+  return reinterpret_cast<const uint4 *>(static_cast<const __bf16 *>(p) + off);
+}
+__device__ __forceinline__ __bf16 bf_at(const uint4 &r, int i) {
+  const uint32_t w = (&r.x)[i >> 1];
+  const unsigned short h = (unsigned short)((i & 1) ? (w >> 16) : (w & 0xffffu));
+  return __builtin_bit_cast(__bf16, h);
+}
+
 template <int MODE>
-__device__ __forceinline__ void load_a(const GemmArgs &g, const float *A, int m0, int k0, int t,
+__device__ __forceinline__ void load_a(const GemmArgs &g, const void *A, int m0, int k0, int t,
                                        Stage &r) {
-  if (MODE == 0) {
+  if (MODE >= 3) {
+    int m, k;
+    if (MODE == 3) { m = t >> 2; k = (t & 3) << 3; } else { k = t >> 3; m = (t & 7) << 3; }
+    const int gm = m0 + m, gk = k0 + k;
+    r.raw = make_uint4(0u, 0u, 0u, 0u);
+    if (gm < g.M && gk < g.K) r.raw = *bp(A, a_off(g, gm, gk));
+  } else if (MODE == 0) {
     for (int q = 0; q < 8; ++q) {
       const int e = t + kThreads * q;
       int m, k;
       if (g.a_kfast) { m = e >> 5; k = e & 31; } else { m = e & 63; k = e >> 6; }
       const int gm = m0 + m, gk = k0 + k;
-      r.v[q] = (gm < g.M && gk < g.K) ? A[a_off(g, gm, gk)] : 0.f;
+      r.v[q] = (gm < g.M && gk < g.K) ? fp(A)[a_off(g, gm, gk)] : 0.f;
     }
   } else {
     for (int q = 0; q < 2; ++q) {
@@ -69,7 +89,7 @@ __device__ __forceinline__ void load_a(const GemmArgs &g, const float *A, int m0
       if (MODE == 1) { m = e >> 3; k = (e & 7) << 2; } else { k = e >> 4; m = (e & 15) << 2; }
       const int gm = m0 + m, gk = k0 + k;
       float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gm < g.M && gk < g.K) x = *reinterpret_cast<const float4 *>(A + a_off(g, gm, gk));
+      if (gm < g.M && gk < g.K) x = *reinterpret_cast<const float4 *>(fp(A) + a_off(g, gm, gk));
       r.v[4 * q] = x.x; r.v[4 * q + 1] = x.y; r.v[4 * q + 2] = x.z; r.v[4 * q + 3] = x.w;
     }
   }
@@ -78,7 +98,12 @@ __device__ __forceinline__ void load_a(const GemmArgs &g, const float *A, int m0
 template <int MODE>
 __device__ __forceinline__ void store_a(__bf16 (*As)[kBK + kPad], int t, const Stage &r,
                                         const GemmArgs &g) {
-  if (MODE == 0) {
+  if (MODE == 3) {
+    *reinterpret_cast<uint4 *>(&As[t >> 2][(t & 3) << 3]) = r.raw;
+  } else if (MODE == 4) {
+    const int k = t >> 3, m = (t & 7) << 3;
+    for (int i = 0; i < 8; ++i) As[m + i][k] = bf_at(r.raw, i);
+  } else if (MODE == 0) {
     for (int q = 0; q < 8; ++q) {
       const int e = t + kThreads * q;
       int m, k;
@@ -100,17 +125,24 @@ __device__ __forceinline__ void store_a(__bf16 (*As)[kBK + kPad], int t, const S
 }
 
 // B tile (32 k x 64 n), staged as Bs[n][k].  Mode 1: four consecutive n per
-// load (n unit-stride); mode 2: four consecutive k.
+// load (n unit-stride); mode 2: four consecutive k; modes 3, 4 the same with
+// eight BF16 values.
 template <int MODE>
-__device__ __forceinline__ void load_b(const GemmArgs &g, const float *B, int n0, int k0, int t,
+__device__ __forceinline__ void load_b(const GemmArgs &g, const void *B, int n0, int k0, int t,
                                        Stage &r) {
-  if (MODE == 0) {
+  if (MODE >= 3) {
+    int n, k;
+    if (MODE == 3) { k = t >> 3; n = (t & 7) << 3; } else { n = t >> 2; k = (t & 3) << 3; }
+    const int gn = n0 + n, gk = k0 + k;
+    r.raw = make_uint4(0u, 0u, 0u, 0u);
+    if (gn < g.N && gk < g.K) r.raw = *bp(B, b_off(g, gk, gn));
+  } else if (MODE == 0) {
     for (int q = 0; q < 8; ++q) {
       const int e = t + kThreads * q;
       int n, k;
       if (g.b_nfast) { n = e & 63; k = e >> 6; } else { n = e >> 5; k = e & 31; }
       const int gn = n0 + n, gk = k0 + k;
-      r.v[q] = (gn < g.N && gk < g.K) ? B[b_off(g, gk, gn)] : 0.f;
+      r.v[q] = (gn < g.N && gk < g.K) ? fp(B)[b_off(g, gk, gn)] : 0.f;
     }
   } else {
     for (int q = 0; q < 2; ++q) {
@@ -119,7 +151,7 @@ __device__ __forceinline__ void load_b(const GemmArgs &g, const float *B, int n0
       if (MODE == 1) { k = e >> 4; n = (e & 15) << 2; } else { n = e >> 3; k = (e & 7) << 2; }
       const int gn = n0 + n, gk = k0 + k;
       float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (gn < g.N && gk < g.K) x = *reinterpret_cast<const float4 *>(B + b_off(g, gk, gn));
+      if (gn < g.N && gk < g.K) x = *reinterpret_cast<const float4 *>(fp(B) + b_off(g, gk, gn));
       r.v[4 * q] = x.x; r.v[4 * q + 1] = x.y; r.v[4 * q + 2] = x.z; r.v[4 * q + 3] = x.w;
     }
   }
@@ -128,7 +160,12 @@ __device__ __forceinline__ void load_b(const GemmArgs &g, const float *B, int n0
 template <int MODE>
 __device__ __forceinline__ void store_b(__bf16 (*Bs)[kBK + kPad], int t, const Stage &r,
                                         const GemmArgs &g) {
-  if (MODE == 0) {
+  if (MODE == 3) {
+    const int k = t >> 3, n = (t & 7) << 3;
+    for (int i = 0; i < 8; ++i) Bs[n + i][k] = bf_at(r.raw, i);
+  } else if (MODE == 4) {
+    *reinterpret_cast<uint4 *>(&Bs[t >> 2][(t & 3) << 3]) = r.raw;
+  } else if (MODE == 0) {
     for (int q = 0; q < 8; ++q) {
       const int e = t + kThreads * q;
       int n, k;
@@ -149,6 +186,21 @@ __device__ __forceinline__ void store_b(__bf16 (*Bs)[kBK + kPad], int t, const S
   }
 }
 
+// Output stores: FP32, or BF16 (rounded to nearest even) when bf16 is set;
+// off counts elements of the output's own type.
+__device__ __forceinline__ void store1(float *p, long long off, float v, int bf16) {
+  if (bf16) reinterpret_cast<__bf16 *>(p)[off] = (__bf16)v;
+  else p[off] = v;
+}
+__device__ __forceinline__ void store4(float *p, long long off, float4 v, int bf16) {
+  if (bf16) {
+    __bf16 *q = reinterpret_cast<__bf16 *>(p) + off;
+    q[0] = (__bf16)v.x; q[1] = (__bf16)v.y; q[2] = (__bf16)v.z; q[3] = (__bf16)v.w;
+  } else {
+    *reinterpret_cast<float4 *>(p + off) = v;
+  }
+}
+
 // LDS: the two operand tiles during the K loop; the 64 x 64 FP32 result
 // (transposed) in the column-major epilogue, after the loop.
 constexpr int kOpBytes = kBM * (kBK + kPad) * 2;
@@ -162,8 +214,10 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
   auto Bs = reinterpret_cast<__bf16 (*)[kBK + kPad]>(smem + kOpBytes);  // [n][k]
   const int b = blockIdx.z;
   const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-  const float *A = g.A + (long long)b * g.sAb;
-  const float *B = g.B + (long long)b * g.sBb;
+  const void *A = AMODE >= 3 ? (const void *)((const __bf16 *)g.A + (long long)b * g.sAb)
+                             : (const void *)(g.A + (long long)b * g.sAb);
+  const void *B = BMODE >= 3 ? (const void *)((const __bf16 *)g.B + (long long)b * g.sBb)
+                             : (const void *)(g.B + (long long)b * g.sBb);
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
@@ -189,10 +243,10 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
     }
     __syncthreads();
   }
-  float *C = g.C + (long long)b * g.sCb;
+  const long long cb = (long long)b * g.sCb;
   if (g.c_mfast) {
     // column-major C: transpose the tile through LDS, then each thread writes
-    // four consecutive rows of one column as a float4
+    // four consecutive rows of one column at once
     auto Cs = reinterpret_cast<float (*)[kCPitch]>(smem);  // [n][m]
     for (int r = 0; r < 16; ++r)
       Cs[wn + (lane & 31)][wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)] = acc[r];
@@ -203,16 +257,15 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
       const int gn = n0 + n, gm = m0 + m;
       if (gn >= g.N || gm >= g.M) continue;
       const float4 c = *reinterpret_cast<const float4 *>(&Cs[n][m]);
-      float4 *dst = reinterpret_cast<float4 *>(C + (long long)gn * g.sCn + gm);
+      const long long go = cb + (long long)gn * g.sCn + gm;
       float4 v = make_float4(g.alpha * c.x, g.alpha * c.y, g.alpha * c.z, g.alpha * c.w);
-      if (g.beta != 0.f) {
-        const float4 o = *dst;
+      if (g.beta != 0.f) {  // FP32 C only (checked by the launcher)
+        const float4 o = *reinterpret_cast<const float4 *>(g.C + go);
         v.x += g.beta * o.x; v.y += g.beta * o.y; v.z += g.beta * o.z; v.w += g.beta * o.w;
       }
       if (g.bias) {
         v.x += g.bias[gm]; v.y += g.bias[gm + 1]; v.z += g.bias[gm + 2]; v.w += g.bias[gm + 3];
       }
-      const long long go = (long long)b * g.sCb + (long long)gn * g.sCn + gm;
       if (g.gelu_z) {
         const float4 zz = *reinterpret_cast<const float4 *>(g.gelu_z + go);
         *reinterpret_cast<float4 *>(g.gelu_out + go) =
@@ -220,10 +273,10 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
                         v.w * gelu_grad(zz.w));
         continue;
       }
-      *dst = v;
+      store4(g.C, go, v, g.c_bf16);
       if (g.gelu_out)
-        *reinterpret_cast<float4 *>(g.gelu_out + go) =
-            make_float4(gelu(v.x), gelu(v.y), gelu(v.z), gelu(v.w));
+        store4(g.gelu_out, go, make_float4(gelu(v.x), gelu(v.y), gelu(v.z), gelu(v.w)),
+               g.gelu_bf16);
     }
     return;
   }
@@ -232,17 +285,16 @@ __global__ void __launch_bounds__(kThreads) k_gemm(GemmArgs g) {
   for (int r = 0; r < 16; ++r) {
     const int row = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (row >= g.M) continue;
-    float *c = C + (long long)row * g.sCm + (long long)col * g.sCn;
+    const long long go = cb + (long long)row * g.sCm + (long long)col * g.sCn;
     float v = g.alpha * acc[r];
-    if (g.beta != 0.f) v += g.beta * *c;
+    if (g.beta != 0.f) v += g.beta * g.C[go];
     if (g.bias) v += g.bias[row];
-    const long long go = (long long)b * g.sCb + (long long)row * g.sCm + (long long)col * g.sCn;
     if (g.gelu_z) {
       g.gelu_out[go] = v * gelu_grad(g.gelu_z[go]);
       continue;
     }
-    *c = v;
-    if (g.gelu_out) g.gelu_out[go] = gelu(v);
+    store1(g.C, go, v, g.c_bf16);
+    if (g.gelu_out) store1(g.gelu_out, go, gelu(v), g.gelu_bf16);
   }
 }
 
@@ -600,36 +652,59 @@ static bool al4(long long v) { return v % 4 == 0; }
 // are all multiples of four floats; the column-major epilogue when C is
 // unit-stride along m under the same conditions (and gelu_out, if any, 16-byte
 // aligned).
+static bool al8(long long v) { return v % 8 == 0; }
+
+template <int AM>
+static void launch_b(const GemmArgs &g, int bm, dim3 grid, hipStream_t s) {
+  switch (bm) {
+    case 0: hipLaunchKernelGGL((k_gemm<AM, 0>), grid, dim3(kThreads), 0, s, g); break;
+    case 1: hipLaunchKernelGGL((k_gemm<AM, 1>), grid, dim3(kThreads), 0, s, g); break;
+    case 2: hipLaunchKernelGGL((k_gemm<AM, 2>), grid, dim3(kThreads), 0, s, g); break;
+    case 3: hipLaunchKernelGGL((k_gemm<AM, 3>), grid, dim3(kThreads), 0, s, g); break;
+    default: hipLaunchKernelGGL((k_gemm<AM, 4>), grid, dim3(kThreads), 0, s, g); break;
+  }
+}
+
 hipError_t launch_gemm(const GemmArgs &g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.K <= 0 || g0.batch <= 0) return hipSuccess;
   GemmArgs g = g0;
-  const bool a16 = (uintptr_t)g.A % 16 == 0 && al4(g.sAb) && al4(g.a_seg_off) &&
-                   (g.a_seg_k >= g.K || al4(g.a_seg_k));
-  const bool b16 = (uintptr_t)g.B % 16 == 0 && al4(g.sBb) && al4(g.b_seg_off) &&
-                   (g.b_seg_k >= g.K || al4(g.b_seg_k));
   int am = 0, bm = 0;
-  if (a16 && g.sAk == 1 && al4(g.K) && al4(g.sAm)) am = 1;
-  else if (a16 && g.sAm == 1 && al4(g.M) && al4(g.sAk)) am = 2;
-  if (b16 && g.sBn == 1 && al4(g.N) && al4(g.sBk)) bm = 1;
-  else if (b16 && g.sBk == 1 && al4(g.K) && al4(g.sBn)) bm = 2;
+  if (g.a_bf16) {  // BF16 operand: eight-element loads only
+    const bool ok = (uintptr_t)g.A % 16 == 0 && al8(g.sAb) && al8(g.a_seg_off) &&
+                    (g.a_seg_k >= g.K || al8(g.a_seg_k));
+    if (ok && g.sAk == 1 && al8(g.K) && al8(g.sAm)) am = 3;
+    else if (ok && g.sAm == 1 && al8(g.M) && al8(g.sAk)) am = 4;
+    else return hipErrorInvalidValue;
+  } else {
+    const bool a16 = (uintptr_t)g.A % 16 == 0 && al4(g.sAb) && al4(g.a_seg_off) &&
+                     (g.a_seg_k >= g.K || al4(g.a_seg_k));
+    if (a16 && g.sAk == 1 && al4(g.K) && al4(g.sAm)) am = 1;
+    else if (a16 && g.sAm == 1 && al4(g.M) && al4(g.sAk)) am = 2;
+  }
+  if (g.b_bf16) {
+    const bool ok = (uintptr_t)g.B % 16 == 0 && al8(g.sBb) && al8(g.b_seg_off) &&
+                    (g.b_seg_k >= g.K || al8(g.b_seg_k));
+    if (ok && g.sBn == 1 && al8(g.N) && al8(g.sBk)) bm = 3;
+    else if (ok && g.sBk == 1 && al8(g.K) && al8(g.sBn)) bm = 4;
+    else return hipErrorInvalidValue;
+  } else {
+    const bool b16 = (uintptr_t)g.B % 16 == 0 && al4(g.sBb) && al4(g.b_seg_off) &&
+                     (g.b_seg_k >= g.K || al4(g.b_seg_k));
+    if (b16 && g.sBn == 1 && al4(g.N) && al4(g.sBk)) bm = 1;
+    else if (b16 && g.sBk == 1 && al4(g.K) && al4(g.sBn)) bm = 2;
+  }
+  if ((g.c_bf16 && g.beta != 0.f) || (g.gelu_z && g.gelu_bf16)) return hipErrorInvalidValue;
   g.c_mfast = (g.sCm == 1 && g.sCn != 1 && al4(g.M) && al4(g.sCn) && al4(g.sCb) &&
                (uintptr_t)g.C % 16 == 0 && (uintptr_t)g.gelu_out % 16 == 0 &&
                (uintptr_t)g.gelu_z % 16 == 0) ? 1 : 0;
   dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, g.batch);
-  dim3 blk(kThreads);
-#define BBSUR_GEMM(AM, BM) hipLaunchKernelGGL((k_gemm<AM, BM>), grid, blk, 0, s, g)
-  switch (am * 3 + bm) {
-    case 0: BBSUR_GEMM(0, 0); break;
-    case 1: BBSUR_GEMM(0, 1); break;
-    case 2: BBSUR_GEMM(0, 2); break;
-    case 3: BBSUR_GEMM(1, 0); break;
-    case 4: BBSUR_GEMM(1, 1); break;
-    case 5: BBSUR_GEMM(1, 2); break;
-    case 6: BBSUR_GEMM(2, 0); break;
-    case 7: BBSUR_GEMM(2, 1); break;
-    default: BBSUR_GEMM(2, 2); break;
+  switch (am) {
+    case 0: launch_b<0>(g, bm, grid, s); break;
+    case 1: launch_b<1>(g, bm, grid, s); break;
+    case 2: launch_b<2>(g, bm, grid, s); break;
+    case 3: launch_b<3>(g, bm, grid, s); break;
+    default: launch_b<4>(g, bm, grid, s); break;
   }
-#undef BBSUR_GEMM
   return hipGetLastError();
 }
 

@@ -24,6 +24,10 @@ struct GemmArgs {
   float *gelu_out;       // optional second output, with C's strides: GELU(C(m, n)), or
                          // with gelu_z set C(m, n) * GELU'(gelu_z(m, n)) instead of C
   const float *gelu_z;
+  // BF16 storage (the pointers above then address __bf16 elements): operand A
+  // or B (staged with eight-element loads; the launcher rejects layouts that do
+  // not allow them), output C (not with beta != 0), the GELU output
+  int a_bf16, b_bf16, c_bf16, gelu_bf16;
 };
 
 }  // namespace bbsur

@@ -103,7 +103,7 @@ Layout layout(const bbsur_model *m, int B) {
   o.S = m->P / o.Kc;
   o.mats = take(m->mats.size());
   o.ones = take(o.Kc);
-  o.h = take((size_t)(m->L + 1) * BW * m->P);
+  o.h = take(((size_t)(m->L + 1) * BW * m->P + 1) / 2);  // BF16 activations h_0..h_L
   o.z = take((size_t)m->L * BW * m->P);
   o.U = take((size_t)m->L * BW * 2 * m->Q);
   o.T1 = take((size_t)BW * 2 * m->mx * m->n2);
@@ -204,6 +204,13 @@ void build_mats(bbsur_model *m) {
     }
 }
 
+// Which GEMM operands are stored as BF16 (the GELU outputs h_l are: every
+// consumer of h_l is a matrix-core operand, rounded to BF16 anyway).
+constexpr unsigned kBfA = 1, kBfB = 2, kBfC = 4, kBfGelu = 8;
+typedef uint16_t bf16_t;  // storage of one BF16 value in host code
+inline float *as_f(bf16_t *p) { return reinterpret_cast<float *>(p); }
+inline const float *as_f(const bf16_t *p) { return reinterpret_cast<const float *>(p); }
+
 // One strided GEMM launch (A may be two-segment along K).
 struct G {
   hipStream_t s;
@@ -211,7 +218,7 @@ struct G {
           long long sAk, int aseg, long long asegoff, const float *B, long long sBb, long long sBk,
           long long sBn, float *C, long long sCb, long long sCm, long long sCn, float beta = 0.f,
           const float *bias = nullptr, float *gelu_out = nullptr,
-          const float *gelu_z = nullptr) const {
+          const float *gelu_z = nullptr, unsigned bf = 0) const {
     GemmArgs g{};
     g.A = A; g.B = B; g.C = C; g.bias = bias;
     g.M = M; g.N = N; g.K = K; g.batch = batch;
@@ -224,6 +231,10 @@ struct G {
     g.beta = beta;
     g.gelu_out = gelu_out;
     g.gelu_z = gelu_z;
+    g.a_bf16 = (bf & kBfA) ? 1 : 0;
+    g.b_bf16 = (bf & kBfB) ? 1 : 0;
+    g.c_bf16 = (bf & kBfC) ? 1 : 0;
+    g.gelu_bf16 = (bf & kBfGelu) ? 1 : 0;
     return hipchk(launch_gemm(g, s), "gemm");
   }
 };
@@ -239,14 +250,16 @@ struct Ctx {
 
 // Truncated forward transform of nb volumes `in` ([nb][n^3]) into spectra
 // `out` ([nb][2][Q]); fx selects plain or Hermitian-weighted x matrix.
-int spectral_forward(const Ctx &c, const float *in, float *out, size_t fx, int nb) {
+// `in` holds BF16 values when in_bf16 (the activations h_l).
+int spectral_forward(const Ctx &c, const float *in, float *out, size_t fx, int nb,
+                     bool in_bf16 = false) {
   const bbsur_model *m = c.m;
   const int n = m->n, mx = m->mx, my = m->my, mz = m->mz;
   const long long n2 = m->n2;
   G g{c.s};
   float *T1 = c.ws + c.o.T1, *T2 = c.ws + c.o.T2;
   int rc = g.run(nb, (int)n2, 2 * mx, n, in, m->P, n, 1, 0, 0, c.mat(fx), 0, 2 * mx, 1, T1,
-                 2LL * mx * n2, 1, n2);
+                 2LL * mx * n2, 1, n2, 0.f, nullptr, nullptr, nullptr, in_bf16 ? kBfA : 0);
   if (!rc)
     rc = g.run(nb, mx * n, 4 * my, 2 * n, T1, 2LL * mx * n2, n, 1, n, (long long)mx * n2,
                c.mat(m->o_fy), 0, 4 * my, 1, T2, 4LL * my * mx * n, 1, (long long)mx * n);
@@ -263,7 +276,7 @@ int spectral_forward(const Ctx &c, const float *in, float *out, size_t fx, int n
 // also stores GELU of the result there (same layout); with zpre != NULL as
 // well it stores result * GELU'(zpre) there instead of the result.
 int spectral_inverse(const Ctx &c, const float *in, float *out, size_t gx, int nb, float beta,
-                     float *act = nullptr, const float *zpre = nullptr) {
+                     float *act = nullptr, const float *zpre = nullptr, bool act_bf16 = false) {
   const bbsur_model *m = c.m;
   const int n = m->n, mx = m->mx, my = m->my, mz = m->mz;
   const long long n2 = m->n2;
@@ -278,19 +291,23 @@ int spectral_inverse(const Ctx &c, const float *in, float *out, size_t gx, int n
                (long long)n * 2 * mz);
   if (!rc)
     rc = g.run(nb, (int)n2, n, 4 * mz, I2, 2LL * n * n * 2 * mz, 2 * mz, 1, 2 * mz,
-               n2 * 2 * mz, c.mat(m->o_gz), 0, n, 1, out, m->P, 1, n2, beta, nullptr, act, zpre);
+               n2 * 2 * mz, c.mat(m->o_gz), 0, n, 1, out, m->P, 1, n2, beta, nullptr, act, zpre,
+               act_bf16 ? kBfGelu : 0);
   return rc;
 }
 
 // grad (M x N) = sum_b sum_p D[b][m][p] H[b][n][p]: split-K partials + fixed-order sum.
-int weight_grad(const Ctx &c, const float *D, const float *H, int M, int N, float *grad) {
+int weight_grad(const Ctx &c, const float *D, const float *H, int M, int N, float *grad,
+                bool h_bf16 = false) {
   const bbsur_model *m = c.m;
   G g{c.s};
   float *part = c.ws + c.o.part;
   for (int b = 0; b < c.B; ++b) {
+    const float *Hb = h_bf16 ? as_f(reinterpret_cast<const bf16_t *>(H) + (size_t)b * N * m->P)
+                             : H + (size_t)b * N * m->P;
     int rc = g.run((int)c.o.S, M, N, (int)c.o.Kc, D + (size_t)b * M * m->P, c.o.Kc, m->P, 1, 0, 0,
-                   H + (size_t)b * N * m->P, c.o.Kc, 1, m->P, part + (size_t)b * c.o.S * M * N,
-                   (long long)M * N, N, 1);
+                   Hb, c.o.Kc, 1, m->P, part + (size_t)b * c.o.S * M * N, (long long)M * N, N, 1,
+                   0.f, nullptr, nullptr, nullptr, h_bf16 ? kBfB : 0);
     if (rc) return rc;
   }
   return hipchk(launch_sum_rows(part, grad, (int)(c.B * c.o.S), M * N, c.ws + c.o.red, c.s),
@@ -344,25 +361,30 @@ int forward(const Ctx &c, const float *prm, const float *x) {
   const int B = c.B, W = m->W;
   const long long BWP = (long long)B * W * m->P;
   G g{c.s};
-  float *h = c.ws + c.o.h, *z = c.ws + c.o.z, *U = c.ws + c.o.U;
+  bf16_t *h = reinterpret_cast<bf16_t *>(c.ws + c.o.h);
+  float *z = c.ws + c.o.z, *U = c.ws + c.o.U;
   int rc = g.run(B, W, (int)m->P, m->cin, prm + m->p_lw, 0, m->cin, 1, 0, 0, x,
-                 (long long)m->cin * m->P, m->P, 1, h, (long long)W * m->P, m->P, 1, 0.f,
-                 prm + m->p_lb);
+                 (long long)m->cin * m->P, m->P, 1, as_f(h), (long long)W * m->P, m->P, 1, 0.f,
+                 prm + m->p_lb, nullptr, nullptr, kBfC);
   for (int l = 0; !rc && l < m->L; ++l) {
-    const float *hin = h + l * BWP;
+    const bf16_t *hin = h + l * BWP;
     float *zl = z + l * BWP;
     float *Ul = U + (size_t)l * B * W * 2 * m->Q;
-    rc = g.run(B, W, (int)m->P, W, prm + m->p_w[l], 0, W, 1, 0, 0, hin, (long long)W * m->P,
-               m->P, 1, zl, (long long)W * m->P, m->P, 1, 0.f, prm + m->p_b[l]);
-    if (!rc) rc = spectral_forward(c, hin, Ul, m->o_fx, B * W);
+    rc = g.run(B, W, (int)m->P, W, prm + m->p_w[l], 0, W, 1, 0, 0, as_f(hin),
+               (long long)W * m->P, m->P, 1, zl, (long long)W * m->P, m->P, 1, 0.f,
+               prm + m->p_b[l], nullptr, nullptr, kBfB);
+    if (!rc) rc = spectral_forward(c, as_f(hin), Ul, m->o_fx, B * W, true);
     if (!rc)
       rc = hipchk(launch_mix(Ul, prm + m->p_r[l], c.ws + c.o.V, B, W, W, (int)m->Q, c.s), "mix");
     // z_l accumulates the inverse transform; h_{l+1} = GELU(z_l) in the same epilogue
-    if (!rc) rc = spectral_inverse(c, c.ws + c.o.V, zl, m->o_gx, B * W, 1.f, h + (l + 1) * BWP);
+    if (!rc)
+      rc = spectral_inverse(c, c.ws + c.o.V, zl, m->o_gx, B * W, 1.f, as_f(h + (l + 1) * BWP),
+                            nullptr, true);
   }
   if (!rc)
-    rc = g.run(B, 1, (int)m->P, W, prm + m->p_pw, 0, W, 1, 0, 0, h + m->L * BWP,
-               (long long)W * m->P, m->P, 1, c.ws + c.o.y, m->P, m->P, 1, 0.f, prm + m->p_pb);
+    rc = g.run(B, 1, (int)m->P, W, prm + m->p_pw, 0, W, 1, 0, 0, as_f(h + m->L * BWP),
+               (long long)W * m->P, m->P, 1, c.ws + c.o.y, m->P, m->P, 1, 0.f, prm + m->p_pb,
+               nullptr, nullptr, kBfB);
   return rc;
 }
 
@@ -372,20 +394,22 @@ int backward(const Ctx &c, const float *prm, const float *x, const float *dy, fl
   const int B = c.B, W = m->W;
   const long long BWP = (long long)B * W * m->P;
   G g{c.s};
-  float *h = c.ws + c.o.h, *z = c.ws + c.o.z, *U = c.ws + c.o.U;
+  const bf16_t *h = reinterpret_cast<const bf16_t *>(c.ws + c.o.h);
+  float *z = c.ws + c.o.z, *U = c.ws + c.o.U;
   float *dh = c.ws + c.o.dh, *dh2 = c.ws + c.o.dh2, *dz = c.ws + c.o.dz;
-  int rc = weight_grad(c, dy, h + m->L * BWP, 1, W, grad + m->p_pw);
+  int rc = weight_grad(c, dy, as_f(h + m->L * BWP), 1, W, grad + m->p_pw, true);
   if (!rc) rc = bias_grad(c, dy, 1, grad + m->p_pb);
   if (!rc)
     rc = g.run(B, W, (int)m->P, 1, prm + m->p_pw, 0, 1, W, 0, 0, dy, m->P, m->P, 1, dh,
                (long long)W * m->P, m->P, 1);
   for (int l = m->L - 1; !rc && l >= 0; --l) {
-    const float *hin = h + l * BWP, *zl = z + l * BWP;
+    const bf16_t *hin = h + l * BWP;
+    const float *zl = z + l * BWP;
     const float *Ul = U + (size_t)l * B * W * 2 * m->Q;
     // dz = dh * GELU'(z_l): for the top layer here, below it in the epilogue of
     // the previous iteration's last inverse-transform stage
     if (l == m->L - 1) rc = hipchk(launch_gelu_bwd(zl, dh, dz, BWP, c.s), "gelu grad");
-    if (!rc) rc = weight_grad(c, dz, hin, W, W, grad + m->p_w[l]);
+    if (!rc) rc = weight_grad(c, dz, as_f(hin), W, W, grad + m->p_w[l], true);
     if (!rc) rc = bias_grad(c, dz, W, grad + m->p_b[l]);
     if (!rc)
       rc = g.run(B, W, (int)m->P, W, prm + m->p_w[l], 0, 1, W, 0, 0, dz, (long long)W * m->P,

@@ -21,33 +21,35 @@ BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix cores
 
 
 def forward_counts(n, cin, W, L, mx, my, mz, B):
-    """Algorithmic bytes (FP32 activations read and written once per launch,
-    weights and transform matrices counted once) and FLOPs of one forward pass
-    of B samples, launch by launch."""
+    """Algorithmic bytes (activations read and written once per launch: the
+    GELU outputs h_l in BF16, everything else FP32; weights and transform
+    matrices counted once) and FLOPs of one forward pass of B samples, launch by
+    launch."""
     P, n2 = n ** 3, n * n
     Q = mx * 2 * my * 2 * mz
     f = 4
-    vol = B * W * P * f                     # one activation tensor
+    vol = B * W * P * f                     # one FP32 activation tensor
+    hb = B * W * P * 2                      # one BF16 tensor h_l
     T1 = B * W * 2 * mx * n2 * f            # after the x stage
     T2 = B * W * 4 * my * mx * n * f        # after the y stage
     U = B * W * 2 * Q * f                   # kept modes (real, imaginary planes)
     I1 = B * W * 2 * n * 4 * mz * my * f    # inverse x stage
     I2 = B * W * 2 * n * n * 2 * mz * f     # inverse y stage
     nb = B * W
-    rows = [("lift", B * cin * P * f + vol, 2 * W * cin * P * B)]
+    rows = [("lift", B * cin * P * f + hb, 2 * W * cin * P * B)]
     for _ in range(L):
         rows += [
-            ("pointwise", 2 * vol + W * W * f, 2 * W * W * P * B),
-            ("dft_x", vol + T1, 2 * n2 * 2 * mx * n * nb),
+            ("pointwise", hb + vol + W * W * f, 2 * W * W * P * B),
+            ("dft_x", hb + T1, 2 * n2 * 2 * mx * n * nb),
             ("dft_y", T1 + T2, 2 * (mx * n) * (4 * my) * (2 * n) * nb),
             ("dft_z", T2 + U, 2 * (2 * my * mx) * (4 * mz) * (2 * n) * nb),
             ("mix", 2 * U + 2 * Q * W * W * f, 8 * Q * W * W * B),
             ("idft_x", U + I1, 2 * (4 * mz * my) * (2 * n) * (2 * mx) * nb),
             ("idft_y", I1 + I2, 2 * (n * 2 * mz) * (2 * n) * (4 * my) * nb),
-            # last stage: reads I2 and z, writes z and GELU(z)
-            ("idft_z_gelu", I2 + 3 * vol, 2 * n2 * n * (4 * mz) * nb),
+            # last stage: reads I2 and z, writes z and h = GELU(z)
+            ("idft_z_gelu", I2 + 2 * vol + hb, 2 * n2 * n * (4 * mz) * nb),
         ]
-    rows.append(("project", vol + B * P * f, 2 * W * P * B))
+    rows.append(("project", hb + B * P * f, 2 * W * P * B))
     return rows
 
 

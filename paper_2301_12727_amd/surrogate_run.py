@@ -131,14 +131,33 @@ def generate(seeds, n=64, device="cuda", chunk=32, keep_masks=False) -> Dataset:
     return ds
 
 
-def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epochs=1000):
-    """Adam on the mean squared error of the log target, cosine-decayed
-    learning rate over a time budget.  Returns (params, loss history)."""
+def val_loss(model, params, x, y, focus, batch=4):
+    """Training objective (weighted MSE of the log map) over a validation set."""
+    import torch
+    pred = torch.empty_like(y)
+    for s in range(0, x.shape[0], batch):
+        model.forward(params, x[s:s + batch], pred[s:s + batch])
+    w = 1.0 + focus * torch.exp(y) if focus > 0 else torch.ones_like(y)
+    return float((w * (pred - y) ** 2).mean())
+
+
+def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epochs=1000,
+          n_val=0, focus=0.0, val_every=5, flips=False):
+    """Adam on the (weighted) mean squared error of the log target,
+    cosine-decayed learning rate over a time budget.  With n_val > 0 the last
+    n_val samples are held out of training and the parameters with the lowest
+    validation loss (checked every val_every epochs and at the end) are kept.
+    With flips, each batch is mirrored in x and/or y at random: the wave
+    equation in isotropic media is mirror-symmetric, so a mirrored patch with
+    its mirrored free field and peak map is another valid sample (up to the
+    half-cell staggering of the grid).  Returns (params, loss history)."""
     import torch
     params = model.init_params(seed)
     st = model.train_state(params)
     rng = np.random.default_rng(seed)
-    N = ds.x.shape[0]
+    N = ds.x.shape[0] - n_val
+    xv, yv = ds.x[N:], ds.y[N:]
+    best, best_val, best_epoch = None, float("inf"), 0
     hist = []
     t0 = time.time()
     steps_per_epoch = N // batch
@@ -150,14 +169,31 @@ def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epoc
             frac = min(1.0, (time.time() - t0) / seconds)
             lr_t = 1e-5 + 0.5 * (lr - 1e-5) * (1 + math.cos(math.pi * frac))
             idx = torch.from_numpy(order[s * batch:(s + 1) * batch]).to(ds.x.device)
-            loss = model.train_step(st, ds.x.index_select(0, idx), ds.y.index_select(0, idx),
-                                    lr=lr_t, sync=(s % 50 == 0))
+            xb, yb = ds.x.index_select(0, idx), ds.y.index_select(0, idx)
+            if flips:
+                dims = [d for d, f in ((4, rng.random() < 0.5), (3, rng.random() < 0.5)) if f]
+                if dims:
+                    xb, yb = torch.flip(xb, dims), torch.flip(yb, dims)
+            loss = model.train_step(st, xb, yb, lr=lr_t, sync=(s % 50 == 0))
             if loss is not None:
                 acc = loss
         epoch += 1
-        hist.append({"epoch": epoch, "loss": acc, "t": round(time.time() - t0, 1)})
-        log(f"[surrogate] epoch {epoch} loss {acc:.4e} ({time.time() - t0:.0f}s)")
-    return st.params, hist
+        rec = {"epoch": epoch, "loss": acc, "t": round(time.time() - t0, 1)}
+        done = not (time.time() - t0 < seconds and epoch < max_epochs)
+        if n_val and (epoch % val_every == 0 or done):
+            v = val_loss(model, st.params, xv, yv, focus, batch)
+            rec["val_loss"] = v
+            if v < best_val:
+                best, best_val, best_epoch = st.params.clone(), v, epoch
+        hist.append(rec)
+        log(f"[surrogate] epoch {epoch} loss {acc:.4e}"
+            + (f" val {rec['val_loss']:.4e}" if "val_loss" in rec else "")
+            + f" ({time.time() - t0:.0f}s)")
+    if best is None:
+        return st.params, hist
+    log(f"[surrogate] keeping epoch {best_epoch} (validation loss {best_val:.4e})")
+    hist.append({"best_epoch": best_epoch, "best_val_loss": best_val})
+    return best, hist
 
 
 def predict(model, params, x, batch=4):
@@ -219,6 +255,10 @@ def main():
     ap.add_argument("--modes", type=int, default=8)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--flips", type=int, default=1,
+                    help="1: mirror training batches in x / y at random")
+    ap.add_argument("--val", type=int, default=200,
+                    help="training samples held out to pick the best epoch (0: keep the last)")
     ap.add_argument("--focus", type=float, default=10.0,
                     help="loss weight 1 + focus * P/P_free (0: plain MSE of the log map)")
     args = ap.parse_args()
@@ -234,7 +274,8 @@ def main():
     ratio = float(np.mean(dtr.peak_post / dtr.free_post))
     model = sg.Surrogate(n=args.n, cin=4, width=args.width, layers=args.layers,
                          mx=args.modes, my=args.modes, mz=args.modes, loss_focus=args.focus)
-    params, hist = train(model, dtr, args.seconds, batch=args.batch, lr=args.lr)
+    params, hist = train(model, dtr, args.seconds, batch=args.batch, lr=args.lr,
+                         n_val=args.val, focus=args.focus, flips=bool(args.flips))
     res = evaluate(model, params, dev, ratio)
     gate = Gate(dtr.stats)
     in_dist = float(np.mean([gate.accepts(s) for s in dev.stats]))
@@ -284,7 +325,7 @@ def main():
     del yb
     out = {"config": {"n": args.n, "width": args.width, "layers": args.layers,
                       "modes": args.modes, "params": model.n_params, "train": args.train,
-                      "loss_focus": args.focus,
+                      "loss_focus": args.focus, "val": args.val, "flips": args.flips,
                       "eval": args.eval, "batch": args.batch, "seconds": args.seconds},
            "generation_s": round(t_gen, 1), "training": hist, "eval": res,
            "train_mean_ratio": ratio, "gate_in_distribution_frac": in_dist,
