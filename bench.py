@@ -49,6 +49,7 @@ def kernel_hash() -> str:
 
 KERNELS = ("velocity_ac", "velocity", "stress_ac", "stress", "step_deep")
 REACH = 3   # cells around a deep tile that its fused step reads
+LARGE_TILES = 2048   # plans with fewer tiles run no fused step
 
 
 def keep_flags(classes):
@@ -72,11 +73,14 @@ def keep_flags(classes):
 
 def tile_kinds(case, info, classes):
     """Kind of every tile as the library assigns it: 0 general, 1 acoustic,
-    2 deep: an acoustic tile that, with REACH cells around it, lies inside the
-    grid and outside the layer, whose reach holds its fluid only (segment
-    classes one row and one plane around it, the material map for the third
-    cell in x) and whose sigma_yy / sigma_zz no elastic segment reads (keep
-    flags 0).  Returns kinds [nz-chunks][row blocks][segments]."""
+    2 deep: an acoustic tile whose rows and planes, with REACH around them, lie
+    inside the grid and outside the layer, that is a whole x segment inside
+    the grid whose recomputed faces beyond the segment (i0-2, i0-1, i0+64) are
+    outside the grid or outside the x layer, whose reach inside the grid holds
+    its fluid only (segment classes one row and one plane around it, the
+    material map for the third cell in x) and whose sigma_yy / sigma_zz no
+    elastic segment reads (keep flags 0); plans of fewer than LARGE_TILES
+    tiles have no deep tiles.  Returns kinds [nz-chunks][row blocks][segments]."""
     import numpy as np
     nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
     R, K = int(info["tile_rows"]), int(info["tile_planes"])
@@ -87,18 +91,23 @@ def tile_kinds(case, info, classes):
     pad = np.ones((nzc * K, nby * R, nseg), dtype=bool)
     pad[:nz, :ny] = seg
     kind = pad.reshape(nzc, K, nby, R, nseg).all(axis=(1, 3)).astype(np.int8)
+    if kind.size < LARGE_TILES:     # small plans do not launch the fused step
+        return kind
     for kc, by, bx in zip(*np.nonzero(kind)):
         i0, j0, k0 = 64 * bx, R * by, K * kc
         k1 = min(k0 + K, nz)
-        if not (i0 - REACH >= L and i0 + 63 + REACH < nx - L and j0 - REACH >= L
-                and j0 + R - 1 + REACH < ny - L and k0 - REACH >= L and k1 - 1 + REACH < nz - L):
+        face_ok = lambda p: p < 0 or p >= nx or L <= p < nx - L
+        x_ok = i0 + 64 <= nx and face_ok(i0 - 2) and face_ok(i0 - 1) and face_ok(i0 + 64)
+        if not (x_ok and j0 - REACH >= L and j0 + R - 1 + REACH < ny - L
+                and k0 - REACH >= L and k1 - 1 + REACH < nz - L):
             continue
         c = classes[k0, j0, bx]
         if not (classes[k0 - 1:k1 + 1, j0 - 1:j0 + R + 1, bx] == c).all():
             continue
         if keep[k0:k1, j0:j0 + R, bx].any():
             continue
-        shell = case.mat[k0 - REACH:k1 + REACH, j0 - REACH:j0 + R + REACH, [i0 - REACH, i0 + 63 + REACH]]
+        xs = [x for x in (i0 - REACH, i0 + 63 + REACH) if 0 <= x < nx]
+        shell = case.mat[k0 - REACH:k1 + REACH, j0 - REACH:j0 + R + REACH, xs]
         if (shell == c - 1).all():
             kind[kc, by, bx] = 2
     return kind
@@ -123,7 +132,9 @@ def algorithmic_bytes(case, info, classes) -> dict:
                 or planes reads sigma_yy / sigma_zz (keep flag).  Layer memories
                 as above.  Capture steps add 8 B/cell (peak read + write).
       step_deep, fused velocity + stress of a deep tile: read sigma_xx and 3
-                velocities, write them = 32 B per cell, + capture as above."""
+                velocities, write them = 32 B per cell; cells in the x layer
+                also read and write the two x memories (16 B); + capture as
+                above."""
     import numpy as np
     nx, ny, nz, L = case.nx, case.ny, case.nz, case.pml
     R, K = int(info["tile_rows"]), int(info["tile_planes"])
@@ -155,7 +166,12 @@ def algorithmic_bytes(case, info, classes) -> dict:
         out["stress" + suffix] = (20 * nf + 8 * nk + 109 * ne + 8 * lf + 24 * le
                                   + 8 * (nf + ne) * cap + cls_bytes * (2 if name == "ac" else 1))
     nd = int((cell_kind == 2).sum())
-    out["step_deep"] = 32 * nd + 8 * nd * cap + nd / 64
+    # deep cells in the x layer also read and write two layer memories
+    xlay = np.zeros(nx, dtype=bool)
+    xlay[:L] = True
+    xlay[nx - L:] = True
+    ndl = int(((cell_kind == 2) & xlay[None, None, :]).sum())
+    out["step_deep"] = 32 * nd + 16 * ndl + 8 * nd * cap + nd / 64
     out["per_cell_update"] = sum(out[k] for k in KERNELS) / case.cells
     out["acoustic_fraction"] = float(fluid.mean())
     out["acoustic_tile_fraction"] = float((cell_kind >= 1).mean())

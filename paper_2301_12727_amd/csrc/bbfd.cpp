@@ -259,8 +259,8 @@ int build_tables(bbfd_plan *pl) {
   return BBFD_OK;
 }
 
-// Tiles from which a single solve's captured steps run as two branches.
-constexpr int kBranchTiles = 2048;
+// Tiles from which a single solve uses the fused step and two branches.
+constexpr int kLargeTiles = 2048;
 
 void layout(bbfd_plan *pl) {
   const bbfd_problem &p = pl->prob;
@@ -297,10 +297,18 @@ void layout(bbfd_plan *pl) {
       if (a + len <= n && a - kDeepReach >= p.pml && a + len - 1 + kDeepReach < n - p.pml) return true;
     return false;
   };
-  pl->deep = fits(p.nx, kSeg) && fits(p.ny, kRows) && fits(p.nz, pl->kchunk);
-  // Side-by-side branches fill the tails of launches that take many rounds of
-  // blocks; small grids are bound by launch and dependency latency instead.
-  pl->branch = pl->n_tiles >= kBranchTiles;
+  // in x a whole segment suffices whose recomputed faces beyond it are outside
+  // the grid or outside the layer (the fused step handles the x layer)
+  auto x_face_ok = [&](int q) { return q < 0 || q >= p.nx || (q >= p.pml && q < p.nx - p.pml); };
+  bool xfit = false;
+  for (int a = 0; a + kSeg <= p.nx; a += kSeg)
+    xfit = xfit || (x_face_ok(a - 2) && x_face_ok(a - 1) && x_face_ok(a + kSeg));
+  // Small grids are bound by launch and dependency latency, not by bytes: a
+  // fifth launch per step costs more than the fused step saves, and
+  // side-by-side branches only fill the tails of launches that take many
+  // rounds of blocks.  Both are used from kLargeTiles tiles up.
+  pl->deep = xfit && fits(p.ny, kRows) && fits(p.nz, pl->kchunk) && pl->n_tiles >= kLargeTiles;
+  pl->branch = pl->n_tiles >= kLargeTiles;
   pl->off_kind = o; o += round_up((size_t)pl->n_tiles, 256);
   pl->off_lists = o; o += round_up(3 * (size_t)pl->n_tiles * sizeof(int), 256);
   pl->off_counts = o; o += 256;
@@ -345,6 +353,7 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.kchunk = pl->kchunk;
   a.nby = (pl->prob.ny + kRows - 1) / kRows;
   a.n_tiles = pl->n_tiles;
+  a.deep = pl->deep ? 1 : 0;
   return a;
 }
 

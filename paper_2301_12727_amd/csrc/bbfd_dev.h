@@ -96,6 +96,7 @@ struct StepArgs {
   int kchunk;             // z cells per tile
   int nby;                // row blocks per plane (rows per block: kRows)
   int n_tiles;            // x segments * row blocks * z chunks
+  int deep;               // 1: tiles may be classified deep (fused step launched)
 };
 
 // Rows of a single-solve tile (one wave per row).

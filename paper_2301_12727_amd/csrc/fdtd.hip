@@ -557,6 +557,33 @@ __device__ __forceinline__ float vnew(float vold, float b, float m1, float p0, f
   return fmaf(b, dfw(m1, p0, p1, p2), vold);
 }
 
+// XL: some face v_x(p), p = i-2 .. i+1, of the wave's recomputed velocities
+// lies in the x absorbing layer or outside the grid.  Inside the layer the
+// recomputation and the own cell's updates add the CPML memory terms exactly
+// as the velocity and stress kernels do (the memories of the faces the wave
+// recomputes but does not own are read only; the tile test keeps them inside
+// the wave's own segment); outside the grid v_x is the zero ghost face, which
+// no kernel updates.
+struct XFace {
+  bool in, ly;   // inside the grid; inside the x layer
+  float tb, ta;  // CPML b and a at the half position p + 1/2
+  __device__ __forceinline__ void set(const StepArgs &A, int p) {
+    const Grid &g = A.g;
+    in = p >= 0 && p < g.nx;
+    ly = in && in_layer(p, g.nx, g.L);
+    const float4 t = ly ? A.pml.x[p] : make_float4(1.f, 0.f, 1.f, 0.f);
+    tb = t.z;
+    ta = t.w;
+  }
+  // new v_x of this face from its x derivative d, memory q and old value
+  __device__ __forceinline__ float vnew(float d, float q, float bu, float vold) const {
+    if (!in) return 0.f;
+    if (ly) d = d + fmaf(tb, q, ta * d);
+    return fmaf(bu, d, vold);
+  }
+};
+
+template <bool XL>
 __device__ __forceinline__ void deep_tile(const StepArgs &A, const float *lut, int bx, int j, int k0,
                                           int k1, float src_c, float src_s, int capture) {
   const Grid &g = A.g;
@@ -587,6 +614,14 @@ __device__ __forceinline__ void deep_tile(const StepArgs &A, const float *lut, i
   float w1 = vz_face(k0 - 1, ldb(vz, o - PL4), s1, s2, s3, s4);
   float w2 = vz_face(k0, ldb(vz, o), s2, s3, s4, s5);
   float w3 = vz_face(k0 + 1, ldb(vz, o + PL4), s3, s4, s5, s6);
+  XFace f2, f1, f0, fp;  // faces i-2, i-1, i, i+1 (XL only)
+  bool lc = false;       // this cell inside the x layer (CPML of exx)
+  float4 tc = make_float4(1.f, 0.f, 1.f, 0.f);
+  if (XL) {
+    f2.set(A, i - 2); f1.set(A, i - 1); f0.set(A, i); fp.set(A, i + 1);
+    lc = in_layer(i, g.nx, g.L);
+    if (lc) tc = A.pml.x[i];
+  }
   for (int k = k0; k < k1; ++k, o += PL4, qo += QL4) {
     // x stencil of sxx on this row and plane, y stencil on this column
     const float xm3 = ldb(sxx, o - 12), xm2 = ldb(sxx, o - 8), xm1 = ldb(sxx, o - 4);
@@ -601,12 +636,30 @@ __device__ __forceinline__ void deep_tile(const StepArgs &A, const float *lut, i
     const float vzn = more ? ldb(vz, o + 2 * PL4) : 0.f;    // plane k + 2
     const float pk = capture ? ldb_once(A.peak, qo) : 0.f;
     // new velocities around the cell (the velocity kernels' acoustic update)
-    const float nx2 = vnew(ux2, b, xm3, xm2, xm1, s3), nx1 = vnew(ux1, b, xm2, xm1, s3, xp1);
-    const float nx0 = vnew(ux0, b, xm1, s3, xp1, xp2), nxp = vnew(uxp, b, s3, xp1, xp2, xp3);
+    float nx2, nx1, nx0, nxp;
+    if (XL) {
+      float *psx = A.psi[0];
+      const float q2 = f2.ly ? ldb(psx, o - 8) : 0.f, q1 = f1.ly ? ldb(psx, o - 4) : 0.f;
+      const float q0 = f0.ly ? ldb_once(psx, o) : 0.f, qp = fp.ly ? ldb(psx, o + 4) : 0.f;
+      const float d0 = dfw(xm1, s3, xp1, xp2);
+      nx2 = f2.vnew(dfw(xm3, xm2, xm1, s3), q2, b, ux2);
+      nx1 = f1.vnew(dfw(xm2, xm1, s3, xp1), q1, b, ux1);
+      nx0 = f0.vnew(d0, q0, b, ux0);
+      nxp = fp.vnew(dfw(s3, xp1, xp2, xp3), qp, b, uxp);
+      if (f0.ly) stb(psx, o, fmaf(f0.tb, q0, f0.ta * d0));  // this face's memory
+    } else {
+      nx2 = vnew(ux2, b, xm3, xm2, xm1, s3); nx1 = vnew(ux1, b, xm2, xm1, s3, xp1);
+      nx0 = vnew(ux0, b, xm1, s3, xp1, xp2); nxp = vnew(uxp, b, s3, xp1, xp2, xp3);
+    }
     const float ny2 = vnew(uy2, b, ym3, ym2, ym1, s3), ny1 = vnew(uy1, b, ym2, ym1, s3, yp1);
     const float ny0 = vnew(uy0, b, ym1, s3, yp1, yp2), nyp = vnew(uyp, b, s3, yp1, yp2, yp3);
     // stress update (the acoustic stress kernels' arithmetic)
-    const float exx = dbw(nx2, nx1, nx0, nxp), eyy = dbw(ny2, ny1, ny0, nyp), ezz = dbw(w0, w1, w2, w3);
+    float exx = dbw(nx2, nx1, nx0, nxp);
+    const float eyy = dbw(ny2, ny1, ny0, nyp), ezz = dbw(w0, w1, w2, w3);
+    if (XL && lc) {
+      const float q9 = ldb_once(A.psi[9], o);
+      exx = cpml_b(A.psi[9], o, q9, tc.x, tc.y, exx);
+    }
     const float sn = fmaf(piu, exx + eyy + ezz, s3);
     stb(A.fo[VX], o, nx0);
     stb(A.fo[VY], o, ny0);
@@ -695,23 +748,38 @@ __global__ void __launch_bounds__(kSeg * kRows)
   __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  deep_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s, A.capture);
+  const int i0 = bx * kSeg;
+  if (i0 - 2 < A.g.L || i0 + kSeg >= A.g.nx - A.g.L)  // faces i0-2 .. i0+64 touch the x layer
+    deep_tile<true>(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s, A.capture);
+  else
+    deep_tile<false>(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s, A.capture);
 }
 
 // Tile kinds of a single solve: 1 when every row segment of the tile has a
 // fluid class on every plane of its chunk (acoustic tile), 2 (deep tile) when
 // moreover
-//  * the tile and its reach for the fused step (3 cells in x, 3 rows and 3
-//    planes around it) lie inside the grid and outside the absorbing layer,
-//  * every cell of that reach holds the tile's fluid: the classes of the
-//    segments one row and one plane around the tile cover it up to two cells
-//    beyond their segment in x, and the index map is read for the third, and
+//  * the tile's rows and planes and 3 around them lie inside the grid and
+//    outside the absorbing layer; in x the tile is a whole segment inside the
+//    grid and may reach into the x layer or past the grid's edge, as long as
+//    every layer face it recomputes is one of its own (deep_x_ok),
+//  * every cell of that reach inside the grid holds the tile's fluid: the
+//    classes of the segments one row and one plane around the tile cover it up
+//    to two cells beyond their segment in x, and the index map is read for the
+//    third, and
 //  * no elastic segment reads sigma_yy or sigma_zz of the tile (keep flags 0:
 //    the fused step stores sigma_xx alone),
-// else 0.  Within that reach every other kernel's velocity update reduces to
+// else 0 (and never 2 where the plan does not launch the fused step, A.deep
+// = 0).  Within that reach every other kernel's velocity update reduces to
 // the acoustic one (shear stresses of fluid edges are zero), so the fused
 // step's recomputed neighbours equal the values the neighbouring tiles store.
 constexpr int kReach = kDeepReach;
+// x extent of a deep tile: a whole segment inside the grid whose recomputed
+// faces beyond the segment (i0-2, i0-1, i0+64) are outside the grid or
+// outside the x layer, so that every layer face it touches is its own.
+__device__ __forceinline__ bool deep_x_ok(const Grid &g, int i0) {
+  auto ok = [&](int p) { return p < 0 || p >= g.nx || !in_layer(p, g.nx, g.L); };
+  return i0 + kSeg <= g.nx && ok(i0 - 2) && ok(i0 - 1) && ok(i0 + kSeg);
+}
 __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
   const Grid &g = A.g;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < A.n_tiles; t += gridDim.x * blockDim.x) {
@@ -730,8 +798,8 @@ __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
     }
     int kd = ac ? 1 : 0;
     const int i0 = bx * kSeg, j0 = by * kRows;
-    if (ac && i0 - kReach >= g.L && i0 + kSeg - 1 + kReach < g.nx - g.L && j0 - kReach >= g.L &&
-        j0 + kRows - 1 + kReach < g.ny - g.L && k0 - kReach >= g.L && k1 - 1 + kReach < g.nz - g.L) {
+    if (ac && A.deep && deep_x_ok(g, i0) && j0 - kReach >= g.L && j0 + kRows - 1 + kReach < g.ny - g.L &&
+        k0 - kReach >= g.L && k1 - 1 + kReach < g.nz - g.L) {
       const int c = A.cls[((long long)j0 * A.nseg + bx) * A.kpad + k0];
       bool deep = true;
       for (int j = j0 - 1; deep && j <= j0 + kRows; ++j) {
@@ -743,10 +811,13 @@ __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
             break;
           }
       }
+      // third cell in x beyond the segment, where it is inside the grid (outside
+      // it the fused step reads only zero ghost faces and stresses)
+      const bool xl = i0 - kReach >= 0, xr = i0 + kSeg - 1 + kReach < g.nx;
       for (int k = k0 - kReach; deep && k < k1 + kReach; ++k)
         for (int j = j0 - kReach; j < j0 + kRows + kReach; ++j)
-          if (A.idx[g.off(i0 - kReach, j, k)] != c - 1 ||
-              A.idx[g.off(i0 + kSeg - 1 + kReach, j, k)] != c - 1) {
+          if ((xl && A.idx[g.off(i0 - kReach, j, k)] != c - 1) ||
+              (xr && A.idx[g.off(i0 + kSeg - 1 + kReach, j, k)] != c - 1)) {
             deep = false;
             break;
           }

@@ -292,14 +292,18 @@ def test_acoustic_and_general_tiles_side_by_side():
     assert np.array_equal(peak.cpu().numpy(), P)
 
 
-def test_deep_tiles_fused_step():
-    """Wide water grid with a solid blob: the interior x segments hold deep
-    tiles, whose fused one-pass step must agree with the oracle and with the
-    two-pass kernels (the profiled solve times the fused kernel separately)."""
-    nx, ny, nz, pml, f = 150, 28, 44, 4, 500e3
+@pytest.mark.parametrize("nx,nz,blob_x", [(150, 44, (20, 40)), (128, 70, (70, 90))])
+def test_deep_tiles_fused_step(nx, nz, blob_x):
+    """Wide water grid with a solid blob: whole x segments hold deep tiles,
+    including segments at the grid's x edges whose fused step also carries
+    the x absorbing layer (left edge for nx = 150, both edges for nx = 128).
+    The one-pass step must agree with the oracle and with the two-pass
+    kernels (the profiled solve times the fused kernel separately).  The grids
+    have enough tiles (over 2048) for the plan to launch the fused step."""
+    ny, pml, f = 64, 4, 500e3
     mats = synth._rows(synth.table1(f)["water"], (1850.0, 2700.0, 1300.0, 80.0, 200.0))
     mat = np.zeros((nz, ny, nx), dtype=np.uint8)
-    mat[20:26, 8:18, 20:40] = 1
+    mat[20:26, 8:18, blob_x[0]:blob_x[1]] = 1
     case = synth.Case("deeptiles", nx, ny, nz, pml, f, 6.0, 70, mats, mat, None)
     dx, zs = case.dx, case.source_plane_z()
     radius = 0.3 * min(nx, ny) * dx
