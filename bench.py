@@ -74,9 +74,9 @@ def keep_flags(classes):
 def tile_kinds(case, info, classes):
     """Kind of every tile as the library assigns it: 0 general, 1 acoustic,
     2 deep: an acoustic tile whose rows and planes, with REACH around them, lie
-    inside the grid and outside the layer, that is a whole x segment inside
-    the grid whose recomputed faces beyond the segment (i0-2, i0-1, i0+64) are
-    outside the grid or outside the x layer, whose reach inside the grid holds
+    inside the grid and outside the layer, whose recomputed x faces beyond its
+    segment (i0-2, i0-1, i0+64) are outside the grid or outside the x layer,
+    whose reach inside the grid holds
     its fluid only (segment classes one row and one plane around it, the
     material map for the third cell in x) and whose sigma_yy / sigma_zz no
     elastic segment reads (keep flags 0); plans of fewer than LARGE_TILES
@@ -97,7 +97,7 @@ def tile_kinds(case, info, classes):
         i0, j0, k0 = 64 * bx, R * by, K * kc
         k1 = min(k0 + K, nz)
         face_ok = lambda p: p < 0 or p >= nx or L <= p < nx - L
-        x_ok = i0 + 64 <= nx and face_ok(i0 - 2) and face_ok(i0 - 1) and face_ok(i0 + 64)
+        x_ok = face_ok(i0 - 2) and face_ok(i0 - 1) and face_ok(i0 + 64)
         if not (x_ok and j0 - REACH >= L and j0 + R - 1 + REACH < ny - L
                 and k0 - REACH >= L and k1 - 1 + REACH < nz - L):
             continue

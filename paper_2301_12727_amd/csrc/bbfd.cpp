@@ -297,11 +297,11 @@ void layout(bbfd_plan *pl) {
       if (a + len <= n && a - kDeepReach >= p.pml && a + len - 1 + kDeepReach < n - p.pml) return true;
     return false;
   };
-  // in x a whole segment suffices whose recomputed faces beyond it are outside
-  // the grid or outside the layer (the fused step handles the x layer)
+  // in x a segment suffices whose recomputed faces beyond it are outside the
+  // grid or outside the layer (the fused step handles the x layer)
   auto x_face_ok = [&](int q) { return q < 0 || q >= p.nx || (q >= p.pml && q < p.nx - p.pml); };
   bool xfit = false;
-  for (int a = 0; a + kSeg <= p.nx; a += kSeg)
+  for (int a = 0; a < p.nx; a += kSeg)
     xfit = xfit || (x_face_ok(a - 2) && x_face_ok(a - 1) && x_face_ok(a + kSeg));
   // Small grids are bound by launch and dependency latency, not by bytes: a
   // fifth launch per step costs more than the fused step saves, and

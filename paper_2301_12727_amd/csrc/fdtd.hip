@@ -587,7 +587,8 @@ template <bool XL>
 __device__ __forceinline__ void deep_tile(const StepArgs &A, const float *lut, int bx, int j, int k0,
                                           int k1, float src_c, float src_s, int capture) {
   const Grid &g = A.g;
-  const int i = bx * kSeg + threadIdx.x;  // deep tiles are whole segments and rows
+  const int i = bx * kSeg + threadIdx.x;  // deep tiles are whole row blocks
+  if (i >= g.nx) return;                   // the grid's last x segment may be partial
   const uint32_t P4 = 4u * (uint32_t)g.pitch, PL4 = 4u * (uint32_t)g.plane;
   const uint32_t QL4 = (uint32_t)(g.ny * g.nx) * 4u;
   const float *sxx = A.f[SXX], *vx = A.f[VX], *vy = A.f[VY], *vz = A.f[VZ];
@@ -759,9 +760,9 @@ __global__ void __launch_bounds__(kSeg * kRows)
 // fluid class on every plane of its chunk (acoustic tile), 2 (deep tile) when
 // moreover
 //  * the tile's rows and planes and 3 around them lie inside the grid and
-//    outside the absorbing layer; in x the tile is a whole segment inside the
-//    grid and may reach into the x layer or past the grid's edge, as long as
-//    every layer face it recomputes is one of its own (deep_x_ok),
+//    outside the absorbing layer; in x the tile may reach into the x layer or
+//    past the grid's edge, as long as every layer face it recomputes is one
+//    of its own (deep_x_ok),
 //  * every cell of that reach inside the grid holds the tile's fluid: the
 //    classes of the segments one row and one plane around the tile cover it up
 //    to two cells beyond their segment in x, and the index map is read for the
@@ -773,12 +774,12 @@ __global__ void __launch_bounds__(kSeg * kRows)
 // the acoustic one (shear stresses of fluid edges are zero), so the fused
 // step's recomputed neighbours equal the values the neighbouring tiles store.
 constexpr int kReach = kDeepReach;
-// x extent of a deep tile: a whole segment inside the grid whose recomputed
-// faces beyond the segment (i0-2, i0-1, i0+64) are outside the grid or
+// x extent of a deep tile: a segment (the last one may be partial) whose
+// recomputed faces beyond it (i0-2, i0-1, i0+64) are outside the grid or
 // outside the x layer, so that every layer face it touches is its own.
 __device__ __forceinline__ bool deep_x_ok(const Grid &g, int i0) {
   auto ok = [&](int p) { return p < 0 || p >= g.nx || !in_layer(p, g.nx, g.L); };
-  return i0 + kSeg <= g.nx && ok(i0 - 2) && ok(i0 - 1) && ok(i0 + kSeg);
+  return ok(i0 - 2) && ok(i0 - 1) && ok(i0 + kSeg);
 }
 __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
   const Grid &g = A.g;
