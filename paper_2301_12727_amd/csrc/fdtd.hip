@@ -1,13 +1,15 @@
 // Viscoelastic FDTD step kernels for gfx950 (BabelBrain Section 2.3, Eq. 1).
 //
-// One time step is four launches over the tiles of a solve (64 x 4 x-y
+// One time step is up to five launches over the tiles of a solve (64 x 4 x-y
 // columns marching over up to 8 planes of z), split once per solve into
 // acoustic tiles (every row segment a single lossless fluid throughout the
-// stencil's reach) and general tiles:
+// stencil's reach), deep tiles (acoustic, with the fused step's whole reach in
+// one fluid) and general tiles:
 //   k_velocity_ac, k_velocity : v^{n-1/2} -> v^{n+1/2} (Eq. 1 rows 1-3) and
 //                the source force on the v_z faces of plane ks (Section 2.3)
 //   k_stress_ac, k_stress     : sigma^n -> sigma^{n+1}, Zener memory
 //                variables, peak |p| capture (Eq. 1 rows 4-9, Section 3.2)
+//   k_step_deep               : both half-steps of a deep tile in one pass
 // All are HBM-bandwidth-bound stencils.  x is the fastest (coalesced) axis
 // and each wave owns one 64-cell row segment, so the segment class (acoustic
 // or elastic branch) is wave-uniform.  Per block the material table is
@@ -694,9 +696,9 @@ __device__ __forceinline__ int wave_row() { return __builtin_amdgcn_readfirstlan
 extern __shared__ __align__(16) float s_lut[];
 
 // Single-solve step kernels.  The tiles of a solve are split once per solve
-// into two lists (acoustic / general, each in tile order); block b of a
-// launch takes list entry xcd_band(b, count) and blocks beyond the list's
-// length exit at once.
+// into three lists (acoustic / general / deep, each in tile order); block b
+// of a launch takes list entry xcd_band(b, count) and blocks beyond the
+// list's length exit at once.
 __global__ void __launch_bounds__(kSeg * kRows)
     k_velocity(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
