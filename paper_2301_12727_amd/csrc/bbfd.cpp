@@ -34,8 +34,8 @@ hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tile
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
                        hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
-hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, uint8_t *keep, const Grid &g, int nseg,
-                           int kpad, const float *lut, hipStream_t s);
+hipError_t launch_classify(const uint8_t *idx, uint8_t *rowu, uint8_t *cls, uint8_t *keep,
+                           const Grid &g, int nseg, int kpad, const float *lut, hipStream_t s);
 hipError_t launch_argmax(const float *P, int nx, int ny, int nz, int L, float *pv, long long *pi,
                          Status *st, hipStream_t s);
 int argmax_partials();
@@ -112,7 +112,7 @@ struct bbfd_plan {
   int nseg = 1;
   int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
-         off_cls = 0, off_keep = 0, off_alt = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
+         off_cls = 0, off_keep = 0, off_rowu = 0, off_alt = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
          ws_bytes = 0;
   int n_tiles = 0;
   bool deep = false;    // some tile can be deep: the fused step is launched
@@ -288,6 +288,7 @@ void layout(bbfd_plan *pl) {
   pl->kpad = (int)round_up((size_t)p.nz, 4) + 4;
   pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->off_keep = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
+  pl->off_rowu = o; o += round_up((size_t)pl->nseg * (p.ny + 4) * (p.nz + 4), 256);
   pl->n_tiles = pl->nseg * (int)((p.ny + kRows - 1) / kRows) * ((p.nz + pl->kchunk - 1) / pl->kchunk);
   // A deep tile needs a whole x segment, a row block and a z chunk with
   // kDeepReach cells around them inside the grid and outside the layer; where
@@ -402,7 +403,8 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
   if ((e = launch_pack(mat, (uint8_t *)(ws + pl->off_idx), pl->g, p.n_materials, &st->flags, s)) !=
       hipSuccess)
     return hip_fail(e, "index pack");
-  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_cls),
+  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_rowu),
+                           (uint8_t *)(ws + pl->off_cls),
                            (uint8_t *)(ws + pl->off_keep), pl->g, pl->nseg, pl->kpad,
                            (const float *)(ws + pl->off_lut), s)) != hipSuccess)
     return hip_fail(e, "segment classes");

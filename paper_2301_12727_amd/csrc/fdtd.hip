@@ -1030,29 +1030,45 @@ __global__ void k_pack_idx(const uint8_t *__restrict__ mat, uint8_t *__restrict_
 
 // Segment classes (see kSeg): m + 1 if every cell within two cells of the
 // segment holds lossless fluid m, else 0.  Reads the padded, ghost-replicated
-// index map, so cells outside the grid count as their edge neighbour.  Written
-// as one z column of kpad bytes per (row, segment).
-__global__ void k_classify(const uint8_t *__restrict__ idx, uint8_t *__restrict__ cls, Grid g,
+// index map, so cells outside the grid count as their edge neighbour.  Two
+// passes: k_row_uniform finds, for every row of the padded grid (two ghost
+// rows and planes on each side) and segment, the index all of the segment's
+// cells and two more on each side in x share (255 where they differ);
+// k_classify then asks the 5 x 5 rows around the segment's own row to agree.
+// Written as one z column of kpad bytes per (row, segment).
+__global__ void k_row_uniform(const uint8_t *__restrict__ idx, uint8_t *__restrict__ rowu, Grid g,
+                              int nseg) {
+  const long long total = (long long)nseg * (g.ny + 4) * (g.nz + 4);
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int sg = (int)(t % nseg);
+    const long long r = t / nseg;
+    const int j = (int)(r % (g.ny + 4)) - kGhost, k = (int)(r / (g.ny + 4)) - kGhost;
+    const int x0 = sg * kSeg;
+    const int xa = x0 - kGhost, xb = min(x0 + kSeg - 1, g.nx - 1) + kGhost;
+    const uint8_t *row = idx + g.off(0, j, k);
+    const int m = row[xa];
+    bool same = true;
+    for (int x = xa + 1; same && x <= xb; ++x) same = row[x] == m;
+    rowu[t] = same ? (uint8_t)m : (uint8_t)255;
+  }
+}
+
+__global__ void k_classify(const uint8_t *__restrict__ rowu, uint8_t *__restrict__ cls, Grid g,
                            int nseg, int kpad, const float *__restrict__ lut) {
   const long long total = (long long)nseg * g.ny * g.nz;
+  const long long rstride = (long long)(g.ny + 4) * nseg;  // one padded plane of rowu
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
     const int k = (int)(t % g.nz);
     const long long r = t / g.nz;
     const int sg = (int)(r % nseg), j = (int)(r / nseg);
-    const int x0 = sg * kSeg;
-    const int xa = x0 - kGhost, xb = min(x0 + kSeg - 1, g.nx - 1) + kGhost;
-    const int m = idx[g.off(x0, j, k)];
+    const uint8_t *c = rowu + (long long)(k + kGhost) * rstride + (long long)(j + kGhost) * nseg + sg;
+    const int m = *c;
     bool ok = m < 255 && lut[m * kLutW + kLossless] != 0.f;
     for (int dk = -kGhost; ok && dk <= kGhost; ++dk)
-      for (int dj = -kGhost; ok && dj <= kGhost; ++dj) {
-        const uint8_t *row = idx + g.off(0, j + dj, k + dk);
-        for (int x = xa; x <= xb; ++x)
-          if (row[x] != m) {
-            ok = false;
-            break;
-          }
-      }
+      for (int dj = -kGhost; ok && dj <= kGhost; ++dj)
+        ok = c[dk * rstride + (long long)dj * nseg] == m;
     cls[r * kpad + k] = ok ? (uint8_t)(m + 1) : (uint8_t)0;
   }
 }
@@ -1242,9 +1258,10 @@ hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_ma
   return hipGetLastError();
 }
 
-hipError_t launch_classify(const uint8_t *idx, uint8_t *cls, uint8_t *keep, const Grid &g, int nseg,
-                           int kpad, const float *lut, hipStream_t s) {
-  hipLaunchKernelGGL(k_classify, dim3(4096), dim3(256), 0, s, idx, cls, g, nseg, kpad, lut);
+hipError_t launch_classify(const uint8_t *idx, uint8_t *rowu, uint8_t *cls, uint8_t *keep,
+                           const Grid &g, int nseg, int kpad, const float *lut, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_uniform, dim3(4096), dim3(256), 0, s, idx, rowu, g, nseg);
+  hipLaunchKernelGGL(k_classify, dim3(4096), dim3(256), 0, s, rowu, cls, g, nseg, kpad, lut);
   hipLaunchKernelGGL(k_keep, dim3(4096), dim3(256), 0, s, cls, keep, g, nseg, kpad);
   return hipGetLastError();
 }
