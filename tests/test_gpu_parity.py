@@ -18,6 +18,8 @@ import synth
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "skull200_oracle.npz")
+GOLDEN400 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "skull400_short_oracle.npz")
 TOL_MAP = 2e-4
 TOL_SRC = 1e-5
 
@@ -241,6 +243,47 @@ def test_skull200_full_size_against_oracle_samples():
     plan.source_rayleigh(case.transducer, src, ws)
     torch.cuda.synchronize()
     assert rel_err_complex(src.cpu().numpy(), ref_src) <= TOL_SRC
+
+
+def test_skull400_full_grid_short_run_against_oracle_samples():
+    """The benchmark's 400x400x520 grid at 700 kHz in the launch configuration
+    it times (captured graph, two branches per step, the fused step of deep
+    tiles including those at the x edges), run for 300 steps so the wave
+    crosses the near skull wall: compare the oracle's stored samples."""
+    g = np.load(GOLDEN400)
+    case = synth.skull400()
+    case.n_steps = int(g["n_steps"])
+    say("[parity] skull400 full grid, short run")
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace()
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device="cuda")
+    plan.source_rayleigh(case.transducer, src, ws)
+    mat = torch.from_numpy(np.ascontiguousarray(case.mat)).cuda()
+    peak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    plan.solve(mat, src, peak, ws)
+    idx, val = plan.status(ws)
+    counts = plan.tile_counts(ws)
+    P = peak.cpu().numpy()
+    del peak, ws
+    torch.cuda.empty_cache()
+    L = case.pml
+    lo = (L + 7) // 8
+    sl = (slice(lo, (case.nz - L) // 8), slice(lo, (case.ny - L) // 8), slice(lo, (case.nx - L) // 8))
+    errs = {
+        "sub8": rel_l2(P[::8, ::8, ::8][sl], g["sub8"].astype(np.float64)[sl]),
+        "xz": rel_l2(P[L:-L, case.ny // 2, L:-L], g["xz"][L:-L, L:-L]),
+        "yz": rel_l2(P[L:-L, L:-L, case.nx // 2], g["yz"][L:-L, L:-L]),
+    }
+    k = int(np.unravel_index(int(g["peak_index"]), P.shape)[0])
+    errs["xy_peak"] = rel_l2(P[k, L:-L, L:-L], g["xy_peak"][L:-L, L:-L])
+    say(f"[parity] skull400 short: {errs}, peak {idx} vs {int(g['peak_index'])}, tiles {counts}")
+    assert counts[2] > 0
+    for v in errs.values():
+        assert v <= TOL_MAP
+    if idx != int(g["peak_index"]):
+        margin = (float(g["peak_value"]) - float(g["second_value"])) / float(g["peak_value"])
+        assert margin <= 1e-5
+        assert abs(P.flat[idx] - float(g["peak_value"])) <= 1e-4 * float(g["peak_value"])
 
 
 def mixed_tile_case(n_steps=90):
