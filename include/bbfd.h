@@ -134,8 +134,11 @@ int bbfd_rayleigh_volume(const bbfd_plan *plan, const bbfd_transducer *t, float 
      workspace (dev)  >= workspace_bytes, 256-byte aligned; no need to clear
    The first solve with a given (mat, src, peak, workspace) captures the time
    loop into a HIP graph owned by the plan; later solves with the same
-   pointers replay it.  Index and divergence errors are detected on the device
-   and reported by bbfd_status. */
+   pointers replay it.  For plans of 2048 tiles or more, each captured step
+   runs as two branches on a second stream the plan owns (the fused step of
+   the deep tiles beside the velocity kernels, then the two stress kernels
+   side by side); the result is the same bit for bit.  Index and divergence
+   errors are detected on the device and reported by bbfd_status. */
 int bbfd_solve(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im, float *peak,
                void *workspace, uint64_t workspace_bytes, void *stream);
 
@@ -151,11 +154,13 @@ int bbfd_solve_direct(const bbfd_plan *plan, const uint8_t *mat, const float *sr
    general tiles [3], and the fused velocity + stress step of the deep tiles
    [4].  A tile (64 x tile_rows x tile_planes cells, see bbfd_plan_info) is
    acoustic when every one of its row segments is of a lossless-fluid class
-   (bbfd_segment_classes) on every plane, and deep when moreover it lies, with
-   3 cells around it, inside the grid and outside the absorbing layer, all of
-   those cells hold one fluid and no elastic segment within two rows or planes
-   reads its sigma_yy or sigma_zz; such tiles run kernels specialised to those
-   cases (bbfd_tile_counts).  Results are identical to bbfd_solve. */
+   (bbfd_segment_classes) on every plane, and deep when moreover its rows and
+   planes clear the y and z absorbing layers by 3 cells, every layer face its
+   fused step recomputes in x is one of its own, all cells within 3 of it
+   inside the grid hold one fluid and no elastic segment within two rows or
+   planes reads its sigma_yy or sigma_zz; such tiles run kernels specialised
+   to those cases (bbfd_tile_counts).  Plans of fewer than 2048 tiles run no
+   fused step.  Results are identical to bbfd_solve. */
 int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
                         float *peak, void *workspace, uint64_t workspace_bytes, void *stream,
                         double *ms_out);
