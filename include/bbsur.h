@@ -37,7 +37,7 @@ extern "C" {
 #endif
 
 typedef struct {
-  int32_t n;      /* cells per axis of the cubic domain */
+  int32_t n;      /* cells per axis of the cubic domain, a multiple of 8 (8 .. 256) */
   int32_t cin;    /* input channels */
   int32_t width;  /* channels of the hidden layers */
   int32_t layers; /* Fourier layers */

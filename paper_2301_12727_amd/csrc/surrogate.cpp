@@ -99,7 +99,8 @@ Layout layout(const bbsur_model *m, int B) {
   const long long BW = (long long)B * m->W;
   // weight gradients contract over all n^3 cells: split them into chunks of
   // n^2 / 16 cells (n^2 for small n) so a gradient launch has 16n blocks
-  o.Kc = (m->n2 % 16 == 0 && m->n2 >= 4096) ? m->n2 / 16 : m->n2;
+  // (a multiple of 8 cells: the BF16 activations are staged eight at a time)
+  o.Kc = (m->n2 % 128 == 0 && m->n2 >= 4096) ? m->n2 / 16 : m->n2;
   o.S = m->P / o.Kc;
   o.mats = take(m->mats.size());
   o.ones = take(o.Kc);
@@ -440,7 +441,8 @@ int bbsur_create(const bbsur_config *cfg, bbsur_model **out) {
   *out = nullptr;
   if (!cfg) return fail(BBFD_EINVAL, "null config");
   const bbsur_config &c = *cfg;
-  if (c.n < 4 || c.n > 256 || c.cin < 1 || c.width < 1 || c.width > 256 || c.layers < 1 ||
+  if (c.n < 8 || c.n > 256 || c.n % 8 != 0 || c.cin < 1 || c.width < 1 || c.width > 256 ||
+      c.layers < 1 ||
       c.mx < 1 || c.my < 1 || c.mz < 1 || 2 * c.mx > c.n || 2 * c.my > c.n || 2 * c.mz > c.n ||
       !(c.loss_focus >= 0.f))
     return fail(BBFD_EINVAL, "bad surrogate configuration");

@@ -107,3 +107,20 @@ def test_tile_shape_reported():
         info = bb.Plan.from_case(case).info
         assert info["tile_rows"] == 4
         assert info["tile_planes"] == planes, (case.name, info["tile_planes"])
+
+
+def test_surrogate_config_validation():
+    """bbsur_create (host only): the grid edge must be a multiple of 8 (the BF16
+    activations are staged eight values at a time), modes must fit the grid,
+    and an accepted network has the oracle network's parameter count."""
+    from oracle import nn_ref
+    from paper_2301_12727_amd import surrogate as sg
+    for kw in (dict(n=12), dict(n=4), dict(n=16, mx=9), dict(n=16, width=0)):
+        args = dict(n=16, cin=4, width=8, layers=2, mx=3, my=3, mz=3)
+        args.update(kw)
+        with pytest.raises(bb.BBFDError) as e:
+            sg.Surrogate(**args)
+        assert e.value.code == bb.EINVAL
+    cfg = nn_ref.Config(n=16, cin=4, width=8, layers=2, mx=3, my=3, mz=3)
+    model = sg.Surrogate(**cfg.__dict__)
+    assert model.n_params == sum(int(np.prod(s)) for _, s in nn_ref.param_layout(cfg))
