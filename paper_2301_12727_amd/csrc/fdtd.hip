@@ -552,9 +552,10 @@ __device__ __forceinline__ void stress_ac_tile(const StepArgs &A, const float *l
 // velocity and stress, and never waits for another tile.  Inputs come from the
 // current buffers and outputs go to the other ones, so neighbouring tiles may
 // run in any order.  Every recomputed value is the acoustic velocity update
-// of the velocity kernels, operation for operation, so the results equal the
-// two-pass step bit for bit.  It moves 32 bytes per cell update (sigma_xx and
-// v read, written) instead of 48.
+// of the velocity kernels, operation for operation (with the CPML memory term
+// for faces in the x layer, see XFace), so the results equal the two-pass step
+// bit for bit.  It moves 32 bytes per cell update (sigma_xx and v read,
+// written) instead of 48.
 __device__ __forceinline__ float vnew(float vold, float b, float m1, float p0, float p1, float p2) {
   return fmaf(b, dfw(m1, p0, p1, p2), vold);
 }
