@@ -335,12 +335,14 @@ def test_acoustic_and_general_tiles_side_by_side():
     assert np.array_equal(peak.cpu().numpy(), P)
 
 
-@pytest.mark.parametrize("nx,nz,blob_x", [(150, 44, (20, 40)), (128, 70, (70, 90))])
+@pytest.mark.parametrize("nx,nz,blob_x", [(150, 44, (20, 40)), (128, 70, (70, 90)),
+                                           (40, 128, (15, 25))])
 def test_deep_tiles_fused_step(nx, nz, blob_x):
     """Wide water grid with a solid blob: x segments hold deep tiles,
     including segments at the grid's x edges whose fused step also carries
     the x absorbing layer (left edge and a partial last segment, 22 cells
-    wide, for nx = 150; both edges for nx = 128).
+    wide, for nx = 150; both edges for nx = 128; both edges within one
+    40-cell segment for nx = 40).
     The one-pass step must agree with the oracle and with the two-pass
     kernels (the profiled solve times the fused kernel separately).  The grids
     have enough tiles (over 2048) for the plan to launch the fused step."""
