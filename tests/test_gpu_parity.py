@@ -335,14 +335,16 @@ def test_acoustic_and_general_tiles_side_by_side():
     assert np.array_equal(peak.cpu().numpy(), P)
 
 
-@pytest.mark.parametrize("nx,nz,blob_x", [(150, 44, (20, 40)), (128, 70, (70, 90)),
-                                           (40, 128, (15, 25))])
-def test_deep_tiles_fused_step(nx, nz, blob_x):
+@pytest.mark.parametrize("nx,nz,blob_x,src_k", [(150, 44, (20, 40), -1), (128, 70, (70, 90), -1),
+                                                 (40, 128, (15, 25), -1), (128, 70, (70, 90), 16)])
+def test_deep_tiles_fused_step(nx, nz, blob_x, src_k):
     """Wide water grid with a solid blob: x segments hold deep tiles,
     including segments at the grid's x edges whose fused step also carries
     the x absorbing layer (left edge and a partial last segment, 22 cells
     wide, for nx = 150; both edges for nx = 128; both edges within one
-    40-cell segment for nx = 40).
+    40-cell segment for nx = 40).  With the source plane moved 12 planes into
+    the interior (src_k = 16) deep tiles also carry the source force on their
+    v_z faces.
     The one-pass step must agree with the oracle and with the two-pass
     kernels (the profiled solve times the fused kernel separately).  The grids
     have enough tiles (over 2048) for the plan to launch the fused step."""
@@ -351,6 +353,7 @@ def test_deep_tiles_fused_step(nx, nz, blob_x):
     mat = np.zeros((nz, ny, nx), dtype=np.uint8)
     mat[20:26, 8:18, blob_x[0]:blob_x[1]] = 1
     case = synth.Case("deeptiles", nx, ny, nz, pml, f, 6.0, 70, mats, mat, None)
+    case.source_k = src_k
     dx, zs = case.dx, case.source_plane_z()
     radius = 0.3 * min(nx, ny) * dx
     focal = 2.4 * radius
