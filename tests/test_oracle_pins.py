@@ -452,3 +452,40 @@ def test_solve_is_linear_in_the_source():
     p2, i2, _ = oracle.solve(prob, case.mat, 2.0 * src)
     np.testing.assert_allclose(p2, 2.0 * p1, rtol=1e-13, atol=0)
     assert i1 == i2
+
+
+def _mirror_case():
+    """A lossy, heterogeneous grid whose materials and source plane are both
+    symmetric under the x reflection about cell 0 of a laterally periodic grid,
+    i -> (nx - i) mod nx (which maps cells to cells and v_x faces to faces):
+    a solid block, a lossy fluid and a bone sliver, random source values."""
+    nx, ny, nz, L = 30, 22, 28, 4
+    mats = synth._rows(synth.table1(500e3)["water"], (1850.0, 2700.0, 1300.0, 80.0, 200.0),
+                       (1050.0, 1560.0, 0.0, 30.0, 0.0))
+    mat = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mat[12:17, 5:13, 0:7] = 1
+    mat[18:22, 8:18, 9:13] = 2
+    case = synth.Case("mirror", nx, ny, nz, L, 500e3, 6.0, 70, mats, mat, None)
+    rng = np.random.default_rng(11)
+    src = rng.normal(size=(ny, nx)) + 1j * rng.normal(size=(ny, nx))
+    m = (-np.arange(nx)) % nx
+    upper = np.arange(nx) > nx // 2
+    mat[:, :, upper] = mat[:, :, m[upper]]
+    src[:, upper] = src[:, m[upper]]
+    return case, src, m
+
+
+def test_solve_is_mirror_symmetric_in_x():
+    """The staggered x operators are antisymmetric under the reflection (v_x
+    faces map to faces, with a sign), so with laterally periodic boundaries
+    symmetric materials and source give a symmetric peak map: exactly, up to
+    the order of additions.  A transposed or shifted x stencil breaks it."""
+    case, src, m = _mirror_case()
+    assert np.array_equal(case.mat, case.mat[:, :, m]) and np.array_equal(src, src[:, m])
+    prob = oracle.problem_from_case(case, mode=oracle.LATERAL_PERIODIC)
+    p, _, _ = oracle.solve(prob, case.mat, src)
+    assert p.max() > 0
+    np.testing.assert_allclose(p, p[:, :, m], rtol=1e-12, atol=1e-12 * p.max())
+    # the same check fails for a source that is not symmetric
+    p2, _, _ = oracle.solve(prob, case.mat, src * np.linspace(1.0, 1.5, case.nx)[None, :])
+    assert np.abs(p2 - p2[:, :, m]).max() > 1e-3 * p2.max()
