@@ -386,3 +386,66 @@ def test_deep_tiles_fused_step(nx, nz, blob_x, src_k):
     b.solve([mat_d], [bsrc], [bpeak], bws)
     b.status(bws, 0)
     assert np.array_equal(bpeak.cpu().numpy(), P)
+
+
+def test_largest_accepted_grid_against_oracle_window():
+    """The largest grid the plan accepts for a 1000 x 1000 cross-section
+    (1000 x 1000 x 1040 cells: every padded field array just under the 4 GiB
+    the step kernels' 32-bit byte offsets address; ragged last x segment of 40
+    cells; deep, general and acoustic tiles).  The source is a random 8 x 8
+    patch on plane 970, near the top of the arrays, beside a solid block.  In 12
+    steps no disturbance travels more than 48 cells (each stencil reaches two
+    cells, two stencils per step), so the peak map inside a 128^3 window around
+    the patch equals the oracle's solve of that window as a grid of its own
+    with the same patch (whose absorbing layers the field never reaches either),
+    and the map outside the window stays exactly zero: a wrapped address
+    would carry the field somewhere else."""
+    NX, NY, NZ, pml, f, steps = 1000, 1000, 1040, 8, 500e3, 12
+    w, ox, oy, oz, ks = 128, 860, 864, 906, 64
+    mats = synth._rows(synth.table1(f)["water"], (1850.0, 2700.0, 1300.0, 80.0, 200.0))
+    small = np.zeros((w, w, w), dtype=np.uint8)
+    small[66:74, 56:72, 58:90] = 1
+    rng = np.random.default_rng(2026)
+    patch = (rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8))).astype(np.complex64)
+    src_s = np.zeros((w, w), dtype=np.complex64)
+    src_s[60:68, 60:68] = patch
+    case = synth.Case("window", w, w, w, pml, f, 6.0, steps, mats, small, None)
+    case.capture_start, case.source_k = 0, ks
+    ref, ridx, _ = oracle.solve(oracle.problem_from_case(case), small, src_s.astype(np.complex128))
+    assert ref.max() > 0
+    # the field stays clear of the window's own absorbing layers
+    reach = np.argwhere(ref > 0)
+    assert reach.min() >= pml and reach.max() < w - pml
+    rk, rj, ri = np.unravel_index(ridx, ref.shape)
+
+    torch.cuda.empty_cache()
+    plan = bb.Plan(NX, NY, NZ, f, 6.0, steps, mats, pml=pml, capture_start=0, source_k=oz + ks)
+    say(f"[parity] largest grid {NX}x{NY}x{NZ}: workspace {plan.workspace_bytes / 2**30:.1f} GiB, "
+        f"free {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB")
+    ws = plan.workspace()
+    mat = np.zeros((NZ, NY, NX), dtype=np.uint8)
+    mat[oz:oz + w, oy:oy + w, ox:ox + w] = small
+    mat_d = torch.from_numpy(mat).cuda()
+    del mat
+    src = torch.zeros((NY, NX), dtype=torch.complex64, device="cuda")
+    src[oy:oy + w, ox:ox + w] = torch.from_numpy(src_s).cuda()
+    peak = torch.empty((NZ, NY, NX), dtype=torch.float32, device="cuda")
+    plan.solve(mat_d, src, peak, ws)
+    idx, val = plan.status(ws)
+    counts = plan.tile_counts(ws)
+    win = peak[oz:oz + w, oy:oy + w, ox:ox + w].cpu().numpy()
+    outside = max(float(peak[:oz].abs().max()), float(peak[oz + w:].abs().max()),
+                  float(peak[oz:oz + w, :oy].abs().max()), float(peak[oz:oz + w, oy + w:].abs().max()),
+                  float(peak[oz:oz + w, oy:oy + w, :ox].abs().max()),
+                  float(peak[oz:oz + w, oy:oy + w, ox + w:].abs().max()))
+    del ws, peak, mat_d, src
+    torch.cuda.empty_cache()
+    err = rel_l2(win, ref)
+    say(f"[parity] largest grid: tiles {counts}, window rel-L2 {err:.3e}, outside max {outside}, "
+        f"peak {np.unravel_index(idx, (NZ, NY, NX))} vs {(oz + rk, oy + rj, ox + ri)}")
+    assert counts[1] > 0 and counts[2] > 0
+    assert err <= TOL_MAP
+    assert outside == 0.0
+    k, j, i = np.unravel_index(idx, (NZ, NY, NX))
+    assert_same_peak(int(np.ravel_multi_index((k - oz, j - oy, i - ox), ref.shape)), ridx, ref, pml)
+    assert val == pytest.approx(float(win[k - oz, j - oy, i - ox]))
