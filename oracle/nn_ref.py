@@ -181,3 +181,18 @@ def init_params(cfg: Config, seed: int) -> np.ndarray:
     p["proj_w"] = rng.normal(0, 1 / math.sqrt(W), (1, W))
     p["proj_b"] = np.zeros(1)
     return pack(p, cfg)
+
+
+def features(mat: np.ndarray, table: np.ndarray, field: np.ndarray) -> np.ndarray:
+    """Input channels of one sample, [4][cells]: the relative sound speed and
+    density c/c_w - 1 and rho/rho_w - 1 of each cell's material (rows of
+    ``table``, [n_table][2]; indices past the table read as 0) and the cosine
+    and sine of the phase of the free field there (phase 0 where the field is
+    exactly zero)."""
+    m = np.asarray(mat).ravel().astype(np.int64)
+    t = np.asarray(table, dtype=np.float64).reshape(-1, 2)
+    inside = m < len(t)
+    row = t[np.where(inside, m, 0)]
+    row[~inside] = 0.0
+    phase = np.angle(np.asarray(field).ravel().astype(np.complex128))
+    return np.stack([row[:, 0], row[:, 1], np.cos(phase), np.sin(phase)])

@@ -153,3 +153,23 @@ def test_weighted_loss_value_and_step():
     assert abs(got - expect) <= 1e-4 * expect
     losses = [model.train_step(st, xs, ts, lr=3e-3) for _ in range(60)]
     assert losses[-1] < 0.5 * got
+
+
+def test_features_match_reference():
+    """Input channels from a material map, a contrast table and a complex free
+    field (ragged cell count; indices past the table; zero and tiny fields)."""
+    rng = np.random.default_rng(8)
+    cells, n_table = 5 * 7 * 11 * 13 + 3, 6
+    mat = rng.integers(0, n_table + 4, cells).astype(np.uint8)
+    table = rng.normal(size=(n_table, 2)).astype(np.float32)
+    field = (rng.normal(size=cells) + 1j * rng.normal(size=cells)).astype(np.complex64)
+    field *= (10.0 ** rng.uniform(-12, 4, cells)).astype(np.float32)
+    field[::97] = 0.0
+    ref = nn_ref.features(mat, table, field)
+    x = torch.empty((4, cells), dtype=torch.float32, device="cuda")
+    sg.features(torch.from_numpy(mat).cuda(), torch.from_numpy(table).cuda(),
+                torch.from_numpy(field).cuda(), x)
+    got = x.cpu().numpy().astype(np.float64)
+    say(f"[features] {cells} cells: phase max err {np.abs(got[2:] - ref[2:]).max():.2e}")
+    np.testing.assert_array_equal(got[:2], ref[:2])
+    np.testing.assert_allclose(got[2:], ref[2:], rtol=0, atol=2e-6)

@@ -51,3 +51,26 @@ def test_spectral_layer_is_band_pass_with_identity_weights():
 def test_param_layout_roundtrip():
     p = nn_ref.init_params(TINY, 3)
     assert np.array_equal(nn_ref.pack(nn_ref.unpack(p, TINY), TINY), p)
+
+
+def test_features_phase_and_table_lookup():
+    """The phase channels give back the field's phase (atan2 of the pair) and
+    do not depend on its magnitude; a zero field reads as phase 0; material
+    indices past the table read as zero contrast."""
+    rng = np.random.default_rng(5)
+    n = 500
+    theta = rng.uniform(-np.pi, np.pi, n)
+    r = 10.0 ** rng.uniform(-20, 3, n)
+    field = r * np.exp(1j * theta)
+    field[:7] = 0.0
+    table = rng.normal(size=(5, 2))
+    mat = rng.integers(0, 8, n).astype(np.uint8)
+    x = nn_ref.features(mat, table, field)
+    assert x.shape == (4, n)
+    np.testing.assert_allclose(np.arctan2(x[3, 7:], x[2, 7:]), theta[7:], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(x[2] ** 2 + x[3] ** 2, 1.0, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(x[2:, :7], [[1.0] * 7, [0.0] * 7])
+    np.testing.assert_allclose(nn_ref.features(mat, table, 3.5 * field)[2:], x[2:], rtol=0, atol=1e-15)
+    for c in range(n):
+        want = table[mat[c]] if mat[c] < 5 else (0.0, 0.0)
+        assert tuple(x[:2, c]) == tuple(want)
