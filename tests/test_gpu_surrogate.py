@@ -173,3 +173,25 @@ def test_features_match_reference():
     say(f"[features] {cells} cells: phase max err {np.abs(got[2:] - ref[2:]).max():.2e}")
     np.testing.assert_array_equal(got[:2], ref[:2])
     np.testing.assert_allclose(got[2:], ref[2:], rtol=0, atol=2e-6)
+
+
+def test_init_params_layout_and_scales():
+    """Seeded initialisation: reproducible per seed, zero biases, lift and
+    pointwise weights normal with standard deviation 1/sqrt(fan-in), spectral
+    weights uniform in [-1/W, 1/W], all in the documented parameter order."""
+    model = sg.Surrogate(**WIDE.__dict__)
+    a = model.init_params(3).cpu().numpy()
+    assert a.size == model.n_params == sum(int(np.prod(s)) for _, s in nn_ref.param_layout(WIDE))
+    assert np.array_equal(a, model.init_params(3).cpu().numpy())
+    assert not np.array_equal(a, model.init_params(4).cpu().numpy())
+    p = nn_ref.unpack(a, WIDE)
+    W = WIDE.width
+    for name, v in p.items():
+        if name.startswith(("lift_b", "proj_b")) or (name[0] == "b" and name[1:].isdigit()):
+            assert np.all(v == 0.0), name
+    for name, fan, tol in (("lift_w", WIDE.cin, 0.2), ("w0", W, 0.05), ("proj_w", W, 0.35)):
+        v = p[name]
+        assert abs(v.mean()) < 4 * tol / np.sqrt(fan) and abs(v.std() * np.sqrt(fan) - 1) < tol, name
+    r = p["r0"]
+    assert np.abs(r).max() <= float(np.float32(1.0 / W)) and abs(r.mean()) < 5e-3 / W
+    assert abs(r.std() * W * np.sqrt(3.0) - 1) < 0.01
