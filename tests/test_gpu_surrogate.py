@@ -195,3 +195,37 @@ def test_init_params_layout_and_scales():
     r = p["r0"]
     assert np.abs(r).max() <= float(np.float32(1.0 / W)) and abs(r.mean()) < 5e-3 / W
     assert abs(r.std() * W * np.sqrt(3.0) - 1) < 0.01
+
+
+def test_forward_at_largest_size_equivariance_and_pointwise_samples():
+    """The largest accepted volume, n = 256 (width 32, 4 layers, 8 modes per
+    axis).  (1) Every layer commutes with circular shifts (the truncated
+    Fourier transforms are periodic and the rest acts per cell), so the output
+    of a shifted input is the shifted output, up to BF16 rounding; a wrong
+    stride or axis in any transform stage breaks this.  (2) With the spectral
+    weights set to zero the network acts per cell, and its output at 512
+    sampled cells equals the FP64 reference run on those cells alone."""
+    cfg = nn_ref.Config(n=256, cin=4, width=32, layers=4, mx=8, my=8, mz=8)
+    model = sg.Surrogate(**cfg.__dict__)
+    params = model.init_params(5)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    x = torch.randn((1, 4) + (cfg.n,) * 3, device="cuda", generator=gen)
+    shifts, dims = (37, 101, 3), (2, 3, 4)
+    y = model.forward(params, x)
+    ys = model.forward(params, torch.roll(x, shifts, dims))
+    eq = float(torch.linalg.norm(torch.roll(y, shifts, dims) - ys) / torch.linalg.norm(ys))
+    p = nn_ref.unpack(params.cpu().numpy(), cfg)
+    small = nn_ref.Config(n=8, cin=4, width=32, layers=4, mx=1, my=1, mz=1)
+    for l in range(cfg.layers):
+        p[f"r{l}"] = np.zeros((2, cfg.q, cfg.width, cfg.width))
+    y0 = model.forward(torch.from_numpy(nn_ref.pack(p, cfg).astype(np.float32)).cuda(), x)
+    for l in range(cfg.layers):
+        p[f"r{l}"] = np.zeros((2, small.q, cfg.width, cfg.width))
+    cells = torch.from_numpy(np.random.default_rng(5).choice(cfg.n ** 3, 512, replace=False)).cuda()
+    xs = x.reshape(4, -1)[:, cells].cpu().numpy().astype(np.float64).reshape(1, 4, 8, 8, 8)
+    ref = nn_ref.forward(nn_ref.pack(p, small), xs, small).ravel()
+    got = y0.reshape(-1)[cells].cpu().numpy()
+    pw = rel(got, ref)
+    say(f"[surrogate] n=256: shift equivariance rel-L2 {eq:.3e}, pointwise samples rel-L2 {pw:.3e}")
+    assert eq < 2e-2
+    assert pw < 2e-2
