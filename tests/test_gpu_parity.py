@@ -163,6 +163,46 @@ def test_graph_replay_is_bitwise_equal_to_direct_and_deterministic():
     assert np.array_equal(outs[0], outs[2])
 
 
+
+def test_two_branch_graph_replays_match_direct_solve():
+    """A plan with over 2048 tiles captures each step as two branches on a
+    second stream.  Replays of that graph, with eager work on the same tensors
+    in between (the peak map overwritten, and a direct solve with another
+    source plane leaving its own state in the workspace), give the
+    direct-launch map bit for bit every time."""
+    nx, ny, nz, pml, f = 128, 64, 70, 4, 500e3
+    mats = synth._rows(synth.table1(f)["water"], (1850.0, 2700.0, 1300.0, 80.0, 200.0))
+    mat = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mat[20:26, 8:18, 70:90] = 1
+    case = synth.Case("branches", nx, ny, nz, pml, f, 6.0, 60, mats, mat, None)
+    case.capture_start = 0
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace()
+    rng = np.random.default_rng(4)
+    plane = np.zeros((ny, nx), dtype=np.complex64)
+    plane[20:44, 40:88] = rng.normal(size=(24, 48)) + 1j * rng.normal(size=(24, 48))
+    src = torch.from_numpy(plane).cuda()
+    mat_d = torch.from_numpy(mat).cuda()
+    peak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    plan.solve(mat_d, src, peak, ws, graph=False)
+    plan.status(ws)
+    direct = peak.cpu().numpy()
+    counts = plan.tile_counts(ws)
+    assert sum(counts) >= 2048 and counts[2] > 0
+    other = torch.roll(src, (5, -9), (0, 1)) * 3.0
+    scratch = torch.empty_like(peak)
+    for r in range(3):
+        plan.solve(mat_d, other, scratch, ws, graph=False)
+        plan.status(ws)
+        peak.fill_(float(r + 7))
+        torch.cuda.synchronize()
+        plan.solve(mat_d, src, peak, ws)
+        plan.status(ws)
+        got = peak.cpu().numpy()
+        say(f"[parity] two-branch graph replay {r}: max |diff| {np.abs(got - direct).max()}")
+        assert np.array_equal(got, direct)
+
+
 def test_linear_in_source():
     case = synth.random_small_case(4, n_steps=80)
     plan = bb.Plan.from_case(case)
