@@ -124,3 +124,17 @@ def test_surrogate_config_validation():
     cfg = nn_ref.Config(n=16, cin=4, width=8, layers=2, mx=3, my=3, mz=3)
     model = sg.Surrogate(**cfg.__dict__)
     assert model.n_params == sum(int(np.prod(s)) for _, s in nn_ref.param_layout(cfg))
+
+
+def test_batch_rejects_empty_and_names_the_bad_problem():
+    """bbfd_batch_create: no problems is EINVAL; an invalid problem fails with
+    that problem's own error code, its index leading the message."""
+    import ctypes as C
+    h = C.c_void_p()
+    assert bb.lib().bbfd_batch_create(None, 0, C.byref(h)) == bb.EINVAL and not h.value
+    good = bb.Plan.from_case(synth.random_small_case(1, n_steps=20))
+    from paper_2301_12727_amd.bbfd import Problem
+    probs = (Problem * 3)(good.problem, good.problem, good.problem)
+    probs[2].pml = 40                  # thicker than the grid allows
+    assert bb.lib().bbfd_batch_create(probs, 3, C.byref(h)) == bb.EINVAL and not h.value
+    assert bb.lib().bbfd_last_error().decode().startswith("problem 2:")
