@@ -489,3 +489,139 @@ def test_solve_is_mirror_symmetric_in_x():
     # the same check fails for a source that is not symmetric
     p2, _, _ = oracle.solve(prob, case.mat, src * np.linspace(1.0, 1.5, case.nx)[None, :])
     assert np.abs(p2 - p2[:, :, m]).max() > 1e-3 * p2.max()
+
+
+# ------------------------------------------------------------- x/y absorbing layers
+
+# Component relabelling under a swap of two axes: (velocities, normal stresses,
+# shear stresses and their memory variables follow the axes they carry).
+_SWAP = {
+    "xz": ((2, 1, 0), {"vx": "vz", "vz": "vx", "sxx": "szz", "szz": "sxx", "sxy": "syz",
+                       "syz": "sxy", "rxx": "rzz", "rzz": "rxx", "rxy": "ryz", "ryz": "rxy"}),
+    "yz": ((1, 0, 2), {"vy": "vz", "vz": "vy", "syy": "szz", "szz": "syy", "sxy": "sxz",
+                       "sxz": "sxy", "ryy": "rzz", "rzz": "ryy", "rxy": "rxz", "rxz": "rxy"}),
+}
+_BONE_T = (1850.0, 2700.0, 1300.0, 80.0, 200.0)
+_LOSSY_FLUID = (1050.0, 1560.0, 0.0, 30.0, 0.0)
+
+
+def _pulse_run(mat, pml, steps, centre, shear, materials, fields=None, probes=None):
+    """Free evolution (no source) of a Gaussian stress pulse: isotropic normal
+    stresses plus a shear component ``shear``; returns the final fields, and
+    the pressure time series at ``probes`` ((i, j, k) cells) if given."""
+    nz, ny, nx = mat.shape
+    prob = oracle._Prob(nx, ny, nz, pml, 500e3, 6.0, steps, np.array(materials))
+    sim = oracle.Sim(prob, mat)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    g = 1e5 * np.exp(-((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2) / 3.0)
+    for f in ("sxx", "syy", "szz"):
+        sim.field(f)[:] = g
+    sim.field(shear)[:] += 0.3 * g
+    series = []
+    for n in range(steps):
+        sim.step(n, None)
+        if probes:
+            p = -(sim.field("sxx") + sim.field("syy") + sim.field("szz")) / 3.0
+            series.append([p[k, j, i] for (i, j, k) in probes])
+    out = {f: sim.field(f).copy() for f in (fields or ())}
+    sim.close()
+    return out, np.array(series)
+
+
+@pytest.mark.parametrize("swap", ["xz", "yz"])
+def test_xy_layers_are_the_z_layer_with_axes_swapped(swap):
+    """The scheme treats the three axes alike, so swapping x (or y) with z in
+    the material map and the initial state must swap every field exactly (up
+    to the order of additions): a lossy heterogeneous cube whose pulse runs
+    into the z layer near a bone slab crossing it, against the same cube with
+    the axes swapped, whose pulse then runs into the x (or y) layer.  Every
+    x/y absorbing-layer term (which staggered coordinate sets its depth, its
+    memory, its side) is thereby tied to the z layer's, which the 1D
+    reflection pin measures.  A half-cell slip of one x or y derivative's
+    layer coordinate makes fields differ by ~1e-2 of their scale."""
+    n, pml, steps = 32, 6, 240
+    mats = [WATER, _BONE_T, _LOSSY_FLUID]
+    mat = np.zeros((n, n, n), np.uint8)
+    mat[:, :, 12:20] = 1               # slab crossing the z layer at both ends
+    mat[20:31, 4:14, 22:30] = 2
+    mat[25:32, 18:26, 3:9] = 1
+    names = oracle.FIELDS
+    c = np.array([15.3, 14.2, n - pml - 5.6])          # pulse near the high z layer
+    a, _ = _pulse_run(mat, pml, steps, c, "sxy", mats, fields=names)
+    axes, rel = _SWAP[swap]
+    cb = c[[2, 1, 0]] if swap == "xz" else c[[0, 2, 1]]
+    b, _ = _pulse_run(np.ascontiguousarray(mat.transpose(axes)), pml, steps, cb, rel["sxy"],
+                      mats, fields=names)
+    assert np.abs(a["peak"]).max() > 0
+    for f in names:
+        want = a[rel.get(f, f)].transpose(axes)
+        scale = np.abs(want).max()
+        assert scale > 0, f
+        assert np.abs(b[f] - want).max() <= 1e-12 * scale, (swap, f)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+@pytest.mark.parametrize("medium", ["water", "bone_slab"])
+def test_cpml_oblique_reflection_from_x_and_y_faces(axis, medium):
+    """A pressure pulse 8 cells from the high x (or y) layer: pressure at three
+    probes 3 cells from the layer (on the pulse's line and 6 cells to either
+    side, so the echo reaching them left the face obliquely) against the same
+    probes in a grid 4x wider along that axis, whose far layer is too far to
+    echo back within the run.  The difference, the layer's reflection, stays
+    below 1 % of the incident amplitude, in water and inside a lossy bone slab
+    that runs through the layer (P and S waves at grazing incidence)."""
+    n, pml, steps = 40, 8, 300
+    mats = [WATER, _BONE_T]
+    ax = 0 if axis == "x" else 1
+    centre = [n // 2, n // 2, n // 2]
+    centre[ax] = n - pml - 8
+    probes = []
+    for d in (-6, 0, 6):
+        p = [n // 2, n // 2, n // 2]
+        p[ax] = n - pml - 3
+        p[1 - ax] += d
+        probes.append(tuple(p))
+
+    def grid(width):
+        shape = [n, n, n]
+        shape[2 - ax] = width
+        mat = np.zeros(shape, np.uint8)
+        if medium == "bone_slab":
+            mat[14:26] = 1
+        return mat
+
+    _, short = _pulse_run(grid(n), pml, steps, centre, "sxy", mats, probes=probes)
+    _, wide = _pulse_run(grid(4 * n), pml, steps, centre, "sxy", mats, probes=probes)
+    inc = np.abs(wide).max(axis=0)
+    assert (inc > 0).all()
+    refl = np.abs(short - wide).max(axis=0) / inc
+    assert (refl < 1e-2).all(), refl
+    assert (refl > 1e-6).all()            # the short grid's layer is within reach
+
+
+# ------------------------------------------------------------- peak voxel ties
+
+def test_peak_voxel_ties_go_to_the_lowest_linear_index():
+    """Two exact ties.  (1) With a zero source the peak map is zero everywhere,
+    and the peak voxel is the first interior cell (L, L, L).  (2) Laterally
+    periodic, uniform source over a water/plate column: every cell of a plane
+    evolves by the same operations on the same values, so each plane of the map
+    is one value repeated bit for bit; the peak voxel is the first cell (0, 0)
+    of the peak plane, not any other of its nx*ny equal cells."""
+    case = synth.random_small_case(7, n_steps=20)
+    prob = oracle.problem_from_case(case)
+    zero = np.zeros((case.ny, case.nx), complex)
+    p, idx, _ = oracle.solve(prob, case.mat, zero)
+    L = case.pml
+    assert p.max() == 0.0
+    assert idx == (L * case.ny + L) * case.nx + L
+    nx, ny, nz = 5, 4, 90
+    col = np.zeros(nz, np.uint8)
+    col[40:43] = 1
+    mat = np.ascontiguousarray(np.broadcast_to(col[:, None, None], (nz, ny, nx)))
+    prob = oracle._Prob(nx, ny, nz, 8, 250e3, 6.0, 500, np.array([WATER, PLATE]),
+                        mode=oracle.LATERAL_PERIODIC)
+    p, idx, _ = oracle.solve(prob, mat, np.full((ny, nx), 1.0 + 0.5j))
+    k = int(np.argmax(p[8:nz - 8, 0, 0])) + 8
+    assert p.max() > 0 and (p == p[:, :1, :1]).all()
+    assert idx == k * ny * nx
