@@ -200,35 +200,54 @@ def load_traffic(kernel: str, workload: str):
     return t.get("kernels", {}).get(kernel)
 
 
-def cpu_baseline(case, sample_steps: int = 8) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, sample_steps: int = 8, single_steps: int = 1) -> dict:
     """FP64 oracle on the host cores: full workload grid, one untimed step
-    (first touch), then ``sample_steps`` timed steps."""
-    import numpy as np
+    (first touch), then ``sample_steps`` timed steps with all threads and
+    ``single_steps`` more with one thread."""
     import oracle
     prob = oracle.problem_from_case(case)
     src = oracle.source_plane(case)
     sim = oracle.Sim(prob, case.mat)
+    threads = int(oracle.lib().omp_get_max_threads())
     sim.step(0, src)
     t0 = time.perf_counter()
     for n in range(1, 1 + sample_steps):
         sim.step(n, src)
     dt = time.perf_counter() - t0
+    prev = oracle.set_threads(1)
+    t1 = time.perf_counter()
+    for n in range(1 + sample_steps, 1 + sample_steps + single_steps):
+        sim.step(n, src)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(prev)
     sim.close()
-    del np
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": case.cells * sample_steps / dt / 1e9, "unit": "Gcell-updates/s",
-            "cores": cores, "kind": "oracle",
-            "sample": f"{case.name}: full grid, {sample_steps} time steps after one untimed "
-                      f"step ({dt:.1f} s, FP64, OpenMP)"}
+            "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "single_thread_value": case.cells * single_steps / dt1 / 1e9,
+            "sample": f"{case.name}: full grid, {sample_steps} time steps on {threads} threads "
+                      f"after one untimed step ({dt:.1f} s), then {single_steps} on one thread "
+                      f"({dt1:.1f} s); FP64, OpenMP"}
 
 
 TUNE_CACHE = os.path.join(ROOT, "paper_2301_12727_amd", "tune_cache.txt")
 
 
-def batched_section(bb, torch, n_solves: int = 32) -> dict:
+def batched_section(bb, torch, n_solves: int = 32, repeats: int = 5) -> dict:
     """Uneven sweep (sizes 96..160 per axis, 250/500/700 kHz, tilted bowls): one
     captured persistent launch for all solves vs the same solves run one after
-    another as plain captured solves.  Both sides include no Rayleigh time."""
+    another as plain captured solves (medians of ``repeats`` timings each).
+    Both sides include no Rayleigh time."""
     import numpy as np
     import synth
     cases = synth.batch_cases(n_solves)
@@ -246,28 +265,35 @@ def batched_section(bb, torch, n_solves: int = 32) -> dict:
     log(f"[bench] batched shape {shape} (autotune {tune_s:.1f} s)")
     b.solve(mats, srcs, peaks, ws)                     # capture + warm
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.solve(mats, srcs, peaks, ws)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    tb = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        b.solve(mats, srcs, peaks, ws)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+    t_batch = float(np.median(tb))
     for i in range(n_solves):
         b.status(ws, i)
-    log(f"[bench] batched sweep {t_batch:.3f} s")
+    log(f"[bench] batched sweep {t_batch:.3f} s (median of {repeats}: "
+        + ", ".join(f"{t:.3f}" for t in tb) + ")")
     plans = [bb.Plan.from_case(c) for c in cases]
     wss = [p.workspace(dev) for p in plans]
     seq = [torch.empty_like(p) for p in peaks]
     for p, w, m, sr, o in zip(plans, wss, mats, srcs, seq):   # capture + warm
         p.solve(m, sr, o, w)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for p, w, m, sr, o in zip(plans, wss, mats, srcs, seq):
-        p.solve(m, sr, o, w)
-    torch.cuda.synchronize()
-    t_seq = time.perf_counter() - t0
+    ts = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        for p, w, m, sr, o in zip(plans, wss, mats, srcs, seq):
+            p.solve(m, sr, o, w)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_seq = float(np.median(ts))
+    log("[bench] sequential repeats " + ", ".join(f"{t:.3f}" for t in ts))
     equal = all(bool(torch.equal(a, c)) for a, c in zip(peaks, seq))
     updates = sum(c.cells * c.n_steps for c in cases)
     log(f"[bench] sequential {t_seq:.3f} s; maps equal {equal}")
-    del np
     return {"solves": n_solves, "batched_solves_per_s": round(n_solves / t_batch, 3),
             "sequential_solves_per_s": round(n_solves / t_seq, 3),
             "speedup": round(t_seq / t_batch, 3),
@@ -275,7 +301,53 @@ def batched_section(bb, torch, n_solves: int = 32) -> dict:
             "shape": {"rows_per_block": shape[0], "blocks": shape[1], "kchunk": shape[2],
                       "tiles": shape[3]},
             "autotune_s": round(tune_s, 2), "maps_equal_to_plain_solves": equal,
+            "repeats": repeats,
             "cells": int(sum(c.cells for c in cases))}
+
+
+def energy_loss_section(bb, torch, repeats: int = 3) -> dict:
+    """The paper's pair of runs per target on the 200x200x280 skull at 500 kHz
+    (3000 steps): the transcranial solve, its water-only companion on the same
+    plan (each pointer set keeps its captured graph) and the energy loss E_L
+    with T_S = sqrt(E_L) on the plane of the water field's peak.  Reports pairs
+    per second (median of ``repeats``) and the reduction's own time."""
+    import numpy as np
+    import synth
+    case = synth.skull200()
+    dev = torch.device("cuda:0")
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace(dev)
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=dev)
+    plan.source_rayleigh(case.transducer, src, ws)
+    ms = torch.from_numpy(case.mat).to(dev)
+    mw = torch.zeros_like(ms)
+    ps = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+    pw = torch.empty_like(ps)
+
+    def pair():
+        plan.solve(ms, src, ps, ws)
+        plan.solve(mw, src, pw, ws)
+        return plan.energy_loss(ms, ps, mw, pw, ws)
+
+    res = pair()                                      # captures both graphs
+    caps = plan.graph_captures
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pair()
+        times.append(time.perf_counter() - t0)
+    assert plan.graph_captures == caps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        plan.energy_loss(ms, ps, mw, pw, ws)
+    t_red = (time.perf_counter() - t0) / 20
+    t = float(np.median(times))
+    log(f"[bench] E_L pair {t:.3f} s: E_L {res[0]:.4f}, T_S {res[1]:.4f}, z_m {res[2]}")
+    return {"workload": case.name, "pairs_per_s": round(1.0 / t, 3), "pair_s": round(t, 4),
+            "e_l": round(res[0], 6), "t_s": round(res[1], 6), "z_m": res[2],
+            "reduction_ms_with_sync": round(t_red * 1e3, 4), "graph_captures": caps}
 
 
 def main():
@@ -403,6 +475,8 @@ def main():
     del ws, mat, src, peak
     torch.cuda.empty_cache()
     out["batched"] = None if args.no_batch else batched_section(bb, torch)
+    torch.cuda.empty_cache()
+    out["energy_loss"] = None if args.no_batch else energy_loss_section(bb, torch)
     torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")

@@ -80,6 +80,7 @@ typedef struct {
   uint64_t cells;             /* nx * ny * nz */
   int32_t tile_rows;          /* step-kernel tile: 64 x tile_rows x tile_planes cells */
   int32_t tile_planes;
+  uint64_t graph_captures;    /* time loops captured so far by bbfd_solve on this plan */
 } bbfd_plan_info;
 
 typedef struct bbfd_plan bbfd_plan;
@@ -134,7 +135,11 @@ int bbfd_rayleigh_volume(const bbfd_plan *plan, const bbfd_transducer *t, float 
      workspace (dev)  >= workspace_bytes, 256-byte aligned; no need to clear
    The first solve with a given (mat, src, peak, workspace) captures the time
    loop into a HIP graph owned by the plan; later solves with the same
-   pointers replay it.  For plans of 2048 tiles or more, each captured step
+   pointers replay it.  A plan keeps the graphs of its 4 most recently used
+   pointer sets (so a skull solve and its water-only companion, or two
+   workspaces, alternate without re-capture; bbfd_plan_info.graph_captures
+   counts captures) and frees a replaced graph only after its last launch
+   has completed.  For plans of 2048 tiles or more, each captured step
    runs as two branches on a second stream the plan owns (the fused step of
    the deep tiles beside the velocity kernels, then the two stress kernels
    side by side); the result is the same bit for bit.  Index and divergence
@@ -172,6 +177,31 @@ int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *
    output may be NULL. */
 int bbfd_status(const bbfd_plan *plan, const void *workspace, int64_t *peak_index,
                 float *peak_value, void *stream);
+
+/* Energy-loss factor of a transcranial solve against its water-only companion
+   (Section 2.4, Eq. 2) and the pressure transmission T_S = sqrt(E_L) (Section
+   3.2):
+     E_L = sum_{x,y} I(x, y, z_m | skull) / sum_{x,y} I(x, y, z_m | water),
+     I = P^2 / (2 rho c_l)   (P the peak-pressure map, rho and c_l of the
+                              cell's material in the table of plan)
+   with the sums over the plane's cells outside the absorbing layer.  Arguments
+   (dev, layouts as bbfd_solve, both solved with this plan's grid and table):
+     mat_skull, peak_skull   map and peak map of the transcranial solve
+     mat_water, peak_water   map (typically all water) and peak map of the
+                             water-only solve
+     z_m                     plane index in [pml, nz - pml), or < 0 for the
+                             plane of the water-only map's peak voxel (largest
+                             value outside the layer, lowest index on ties)
+     workspace (dev)         a solve workspace of this plan; only its
+                             reduction scratch is used (enqueue after, or on the
+                             stream of, the solves that share it)
+     out (host)              5 doubles: E_L, T_S, z_m, the skull sum, the
+                             water sum (W m^-2 summed over cells)
+   Waits for stream.  BBFD_EDIVERGED when the water-only sum is not positive
+   and finite; BBFD_EINVAL for a plane outside the interior. */
+int bbfd_energy_loss(const bbfd_plan *plan, const uint8_t *mat_skull, const float *peak_skull,
+                     const uint8_t *mat_water, const float *peak_water, int32_t z_m,
+                     void *workspace, uint64_t workspace_bytes, void *stream, double *out);
 
 /* Diagnostic: the row-segment classes the last solve in this workspace used.
    Row segment s of row (j, k) covers cells x in [64 s, min(64 s + 64, nx)); its

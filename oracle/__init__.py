@@ -85,6 +85,16 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> int:
+    """Thread count of the oracle's OpenMP loops from now on (libgomp's
+    omp_set_num_threads, reached through the oracle library's own handle);
+    returns the previous maximum."""
+    L = lib()
+    prev = int(L.omp_get_max_threads())
+    L.omp_set_num_threads(C.c_int(int(n)))
+    return prev
+
+
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 

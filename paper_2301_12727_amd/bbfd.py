@@ -48,7 +48,8 @@ class PlanInfo(C.Structure):
                 ("steps_per_period", C.c_int32), ("capture_start", C.c_int32),
                 ("source_k", C.c_int32), ("pitch", C.c_int32),
                 ("workspace_bytes", C.c_uint64), ("cells", C.c_uint64),
-                ("tile_rows", C.c_int32), ("tile_planes", C.c_int32)]
+                ("tile_rows", C.c_int32), ("tile_planes", C.c_int32),
+                ("graph_captures", C.c_uint64)]
 
 
 EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
@@ -57,7 +58,7 @@ EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_segment_classes", "bbfd_tile_counts",
            "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
            "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
-           "bbfd_batch_status", "bbfd_batch_autotune"]
+           "bbfd_batch_status", "bbfd_batch_autotune", "bbfd_energy_loss"]
 
 _lib = None
 
@@ -83,6 +84,7 @@ def lib():
         L.bbfd_solve_direct.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
         L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
         L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
+        L.bbfd_energy_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, C.c_uint64, vp, vp]
         L.bbfd_segment_classes.argtypes = [vp, vp, vp, C.c_uint64, vp]
         L.bbfd_tile_counts.argtypes = [vp, vp, vp, vp]
         L.bbfd_last_error.restype = C.c_char_p
@@ -162,6 +164,13 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(self.info["workspace_bytes"])
 
+    @property
+    def graph_captures(self) -> int:
+        """Time loops bbfd_solve has captured on this plan so far."""
+        info = PlanInfo()
+        _check(lib().bbfd_plan_get_info(self.h, C.byref(info)))
+        return int(info.graph_captures)
+
     def material_constants(self) -> np.ndarray:
         out = np.empty((self.n_materials, 9), dtype=np.float64)
         _check(lib().bbfd_material_constants(self.h, out.ctypes.data_as(C.c_void_p),
@@ -203,6 +212,19 @@ class Plan:
         _check(fn(self.h, C.c_void_p(mat.data_ptr()), C.c_void_p(src.data_ptr()),
                   C.c_void_p(peak.data_ptr()), C.c_void_p(ws.data_ptr()),
                   ws.numel() * ws.element_size(), C.c_void_p(_stream(stream))))
+
+    def energy_loss(self, mat_skull, peak_skull, mat_water, peak_water, ws, z_m=-1, stream=None):
+        """bbfd_energy_loss: (E_L, T_S, z_m, skull plane sum, water plane sum) of
+        a transcranial solve against its water-only companion (waits)."""
+        out = np.zeros(5, dtype=np.float64)
+        _check(lib().bbfd_energy_loss(self.h, C.c_void_p(mat_skull.data_ptr()),
+                                      C.c_void_p(peak_skull.data_ptr()),
+                                      C.c_void_p(mat_water.data_ptr()),
+                                      C.c_void_p(peak_water.data_ptr()), int(z_m),
+                                      C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                      C.c_void_p(_stream(stream)),
+                                      out.ctypes.data_as(C.c_void_p)))
+        return float(out[0]), float(out[1]), int(out[2]), float(out[3]), float(out[4])
 
     def solve_profiled(self, mat, src, peak, ws, stream=None):
         """Direct-launch solve with per-kernel HIP events on the launch stream;

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbbfd.so")
 
-SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip", "surrogate.cpp", "nn.hip"]
+SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip", "energy.hip", "surrogate.cpp", "nn.hip"]
 # The step kernels spell out every fused multiply-add (fmaf) and must not get
 # others from the compiler: every code path then rounds a cell identically.
 EXTRA = {"fdtd.hip": ["-ffp-contract=off"]}

@@ -46,6 +46,12 @@ hipError_t launch_batched_step(int by, const BatchWalk *W, const float2 *coef, c
 hipError_t launch_batch_split(const BatchTile *tiles, int n, const int *solve_end, int n_solves,
                               int *table_ac, int *table_gen, int *scan, int *len_ac, int *len_gen,
                               hipStream_t s);
+hipError_t launch_plane_energy(const uint8_t *mat_s, const float *p_s, const uint8_t *mat_w,
+                               const float *p_w, int nx, int ny, int L, int z_m, const Status *st,
+                               const double *inv_z, int n_mat, double2 *part, double *out,
+                               hipStream_t s);
+int energy_out_doubles();
+int energy_partials();
 }  // namespace bbfd
 
 using namespace bbfd;
@@ -101,6 +107,7 @@ struct bbfd_plan {
   double dx = 0, dt = 0, omega = 0, cmax = 0, d0 = 0;
   int nt = 0, cap = 0, ks = 0;
   std::vector<double> consts;  // 9 per material
+  std::vector<double> inv_z;   // 1 / (2 rho c_l) per material (plane intensity sums)
   Grid g{};
   std::vector<float> lut;      // n_materials x kLutW
   std::vector<float4> pmltab;  // nx + ny + nz entries
@@ -113,6 +120,7 @@ struct bbfd_plan {
   int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
          off_cls = 0, off_keep = 0, off_rowu = 0, off_alt = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
+         off_energy = 0,
          ws_bytes = 0;
   int n_tiles = 0;
   bool deep = false;    // some tile can be deep: the fused step is launched
@@ -121,9 +129,19 @@ struct bbfd_plan {
   hipStream_t cap_stream = nullptr;
   hipStream_t side_stream = nullptr;  // second branch of the captured steps
   hipEvent_t fork = nullptr, join = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  const void *key[4] = {nullptr, nullptr, nullptr, nullptr};
+  // Captured time loops, one per pointer set (mat, src, peak, workspace), at
+  // most kGraphCache of them, least recently used replaced first.  `done` is
+  // recorded after every launch; a graph is destroyed only once it has run.
+  struct Captured {
+    const void *key[4];
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipEvent_t done;
+    uint64_t used;
+  };
+  std::vector<Captured> graphs;
+  uint64_t clock = 0;
+  uint64_t captures = 0;
 };
 
 namespace {
@@ -215,6 +233,9 @@ void pml_coeff(const bbfd_plan *pl, int n, double xi, float *b, float *a) {
 int build_tables(bbfd_plan *pl) {
   const bbfd_problem &p = pl->prob;
   pl->lut.assign((size_t)p.n_materials * kLutW, 0.0f);
+  pl->inv_z.resize(p.n_materials);
+  for (int m = 0; m < p.n_materials; ++m)
+    pl->inv_z[m] = 1.0 / (2.0 * pl->mats[m].rho * pl->mats[m].c_l);
   pl->pmltab.resize((size_t)p.nx + p.ny + p.nz);
   const double s = pl->dt / pl->dx;
   for (int m = 0; m < p.n_materials; ++m) {
@@ -261,6 +282,8 @@ int build_tables(bbfd_plan *pl) {
 
 // Tiles from which a single solve uses the fused step and two branches.
 constexpr int kLargeTiles = 2048;
+// Captured time loops a plan keeps (distinct pointer sets).
+constexpr int kGraphCache = 4;
 
 void layout(bbfd_plan *pl) {
   const bbfd_problem &p = pl->prob;
@@ -313,6 +336,9 @@ void layout(bbfd_plan *pl) {
   pl->off_kind = o; o += round_up((size_t)pl->n_tiles, 256);
   pl->off_lists = o; o += round_up(3 * (size_t)pl->n_tiles * sizeof(int), 256);
   pl->off_counts = o; o += 256;
+  // energy-loss reduction: a status block for the water map's peak voxel, the
+  // result, the block partials
+  pl->off_energy = o; o += round_up(256 + 256 + (size_t)energy_partials() * 16, 256);
   pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
   pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
   pl->off_alt = o; o += (size_t)kNOut * g.stride * sizeof(float);  // second buffers of v, sigma_ii
@@ -382,13 +408,17 @@ int ensure_pinned(bbfd_plan *pl) {
 
 // Per-solve prologue: tables, cleared state/peak/status, packed index map,
 // segment classes.
-int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char *ws, hipStream_t s) {
+// With pinned = false the tables are uploaded from the plan's own (pageable)
+// host vectors instead of its pinned copies, so no pinned staging is needed.
+int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char *ws, hipStream_t s,
+                     bool pinned = true) {
   const bbfd_problem &p = pl->prob;
   hipError_t e;
-  if ((e = hipMemcpyAsync(ws + pl->off_lut, pl->h_lut, (size_t)p.n_materials * kLutW * sizeof(float),
+  if ((e = hipMemcpyAsync(ws + pl->off_lut, pinned ? pl->h_lut : pl->lut.data(),
+                          (size_t)p.n_materials * kLutW * sizeof(float),
                           hipMemcpyHostToDevice, s)) != hipSuccess)
     return hip_fail(e, "LUT upload");
-  if ((e = hipMemcpyAsync(ws + pl->off_pml, pl->h_pml,
+  if ((e = hipMemcpyAsync(ws + pl->off_pml, pinned ? pl->h_pml : pl->pmltab.data(),
                           ((size_t)p.nx + p.ny + p.nz) * sizeof(float4), hipMemcpyHostToDevice,
                           s)) != hipSuccess)
     return hip_fail(e, "layer-table upload");
@@ -443,9 +473,10 @@ hipError_t link(hipStream_t from, hipStream_t to, hipEvent_t ev) {
 // with blocks of the other.
 constexpr int kStepKernels = 5;
 int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
-                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr, hipStream_t side = nullptr) {
+                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr, hipStream_t side = nullptr,
+                  bool pinned = true) {
   const bbfd_problem &p = pl->prob;
-  int rc = enqueue_prologue(pl, mat, peak, ws, s);
+  int rc = enqueue_prologue(pl, mat, peak, ws, s, pinned);
   if (rc) return rc;
   hipError_t e;
   StepArgs a = step_args(pl, mat, src, peak, ws);
@@ -505,6 +536,17 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
     for (int f = 0; f < kNOut; ++f) std::swap(cur[f], nxt[f]);
   }
   return enqueue_epilogue(pl, peak, ws, s);
+}
+
+// Waits for the last launch of a cached graph, then frees it.
+void release_graph(bbfd_plan::Captured &c) {
+  if (c.done) {
+    (void)hipEventSynchronize(c.done);
+    (void)hipEventDestroy(c.done);
+  }
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  if (c.graph) (void)hipGraphDestroy(c.graph);
+  c = bbfd_plan::Captured{};
 }
 
 int check_solve_args(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
@@ -613,8 +655,7 @@ int bbfd_plan_create(const bbfd_problem *problem, bbfd_plan **out) {
 
 void bbfd_plan_destroy(bbfd_plan *pl) {
   if (!pl) return;
-  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
-  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  for (auto &c : pl->graphs) release_graph(c);
   if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
   if (pl->side_stream) (void)hipStreamDestroy(pl->side_stream);
   if (pl->fork) (void)hipEventDestroy(pl->fork);
@@ -637,6 +678,7 @@ int bbfd_plan_get_info(const bbfd_plan *pl, bbfd_plan_info *out) {
   out->cells = (uint64_t)pl->prob.nx * pl->prob.ny * pl->prob.nz;
   out->tile_rows = kRows;
   out->tile_planes = pl->kchunk;
+  out->graph_captures = pl->captures;
   return BBFD_OK;
 }
 
@@ -762,9 +804,10 @@ int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float
   std::lock_guard<std::mutex> lock(pl->mu);
   if ((rc = ensure_pinned(pl))) return rc;
   const void *key[4] = {mat, src, peak, workspace};
-  if (!pl->exec || std::memcmp(key, pl->key, sizeof key) != 0) {
-    if (pl->exec) { (void)hipGraphExecDestroy(pl->exec); pl->exec = nullptr; }
-    if (pl->graph) { (void)hipGraphDestroy(pl->graph); pl->graph = nullptr; }
+  bbfd_plan::Captured *hit = nullptr;
+  for (auto &c : pl->graphs)
+    if (std::memcmp(key, c.key, sizeof key) == 0) hit = &c;
+  if (!hit) {
     hipError_t e;
     if (!pl->cap_stream &&
         (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess)
@@ -776,26 +819,79 @@ int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float
       return hip_fail(e, "capture event");
     if (!pl->join && (e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming)) != hipSuccess)
       return hip_fail(e, "capture event");
-    if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    if (pl->graphs.size() >= (size_t)kGraphCache) {  // replace the least recently used
+      size_t lru = 0;
+      for (size_t q = 1; q < pl->graphs.size(); ++q)
+        if (pl->graphs[q].used < pl->graphs[lru].used) lru = q;
+      release_graph(pl->graphs[lru]);
+      pl->graphs.erase(pl->graphs.begin() + (long)lru);
+    }
+    bbfd_plan::Captured c{};
+    std::memcpy(c.key, key, sizeof key);
+    if ((e = hipEventCreateWithFlags(&c.done, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "graph event");
+    if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+      release_graph(c);
       return hip_fail(e, "begin capture");
+    }
     rc = enqueue_solve(pl, mat, src, peak, (char *)workspace, pl->cap_stream, nullptr,
                        pl->branch ? pl->side_stream : nullptr);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(pl->cap_stream, &g);
-    if (rc) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
+    e = hipStreamEndCapture(pl->cap_stream, &c.graph);
+    if (rc || e != hipSuccess) {
+      release_graph(c);
+      return rc ? rc : hip_fail(e, "end capture");
     }
-    if (e != hipSuccess) return hip_fail(e, "end capture");
-    pl->graph = g;
-    if ((e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
-      pl->exec = nullptr;
+    if ((e = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0)) != hipSuccess) {
+      c.exec = nullptr;
+      release_graph(c);
       return hip_fail(e, "graph instantiate");
     }
-    std::memcpy(pl->key, key, sizeof key);
+    ++pl->captures;
+    pl->graphs.push_back(c);
+    hit = &pl->graphs.back();
   }
-  hipError_t e = hipGraphLaunch(pl->exec, (hipStream_t)stream);
+  hit->used = ++pl->clock;
+  hipError_t e = hipGraphLaunch(hit->exec, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
+  if ((e = hipEventRecord(hit->done, (hipStream_t)stream)) != hipSuccess)
+    return hip_fail(e, "graph event record");
+  return BBFD_OK;
+}
+
+int bbfd_energy_loss(const bbfd_plan *pl, const uint8_t *mat_skull, const float *peak_skull,
+                     const uint8_t *mat_water, const float *peak_water, int32_t z_m,
+                     void *workspace, uint64_t bytes, void *stream, double *out) {
+  if (!pl || !out) return fail(BBFD_EINVAL, "null argument");
+  if (!mat_skull || !peak_skull || !mat_water || !peak_water)
+    return fail(BBFD_EINVAL, "null device pointer");
+  int rc = check_ws(pl, workspace, bytes);
+  if (rc) return rc;
+  const bbfd_problem &p = pl->prob;
+  if (z_m >= 0 && (z_m < p.pml || z_m >= p.nz - p.pml))
+    return fail(BBFD_EINVAL, "plane %d outside the interior [%d, %d)", z_m, p.pml, p.nz - p.pml);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  Status *st = (Status *)(ws + pl->off_energy);
+  double *res = (double *)(ws + pl->off_energy + 256);
+  double2 *part = (double2 *)(ws + pl->off_energy + 512);
+  hipError_t e;
+  if (z_m < 0) {  // plane of the water-only map's peak voxel
+    if ((e = launch_fill((float *)st, 256 / sizeof(float), 0.f, s)) != hipSuccess ||
+        (e = launch_argmax(peak_water, p.nx, p.ny, p.nz, p.pml, (float *)(ws + pl->off_pv),
+                           (long long *)(ws + pl->off_pi), st, s)) != hipSuccess)
+      return hip_fail(e, "water peak voxel");
+  }
+  if ((e = launch_plane_energy(mat_skull, peak_skull, mat_water, peak_water, p.nx, p.ny, p.pml, z_m,
+                               st, pl->inv_z.data(), p.n_materials, part, res, s)) != hipSuccess)
+    return hip_fail(e, "plane energy launch");
+  double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int nd = energy_out_doubles();
+  if ((e = hipMemcpyAsync(h, res, (size_t)nd * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "energy read");
+  for (int q = 0; q < 5; ++q) out[q] = h[q];
+  if (!(h[4] > 0.0) || !std::isfinite(h[3]) || !std::isfinite(h[4]))
+    return fail(BBFD_EDIVERGED, "water-only plane sum %g is not positive and finite", h[4]);
   return BBFD_OK;
 }
 
@@ -865,6 +961,10 @@ struct bbfd_batch {
   float2 *h_coef = nullptr;
   int *h_cap = nullptr;
   int *h_end = nullptr;
+  // Recorded after every enqueue that reads the pinned staging above (graph
+  // launches included: their table uploads read it when they execute).  The
+  // staging is rewritten, and a graph destroyed, only once it has completed.
+  hipEvent_t staged = nullptr;
   std::mutex mu;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -931,6 +1031,8 @@ int batch_pinned(bbfd_batch *b) {
     return hip_fail(e, "pinned capture allocation");
   if ((e = hipHostMalloc((void **)&b->h_end, n * sizeof(int), hipHostMallocDefault)) != hipSuccess)
     return hip_fail(e, "pinned tile-range allocation");
+  if ((e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "staging event");
   for (size_t s = 0; s < n; ++s) {
     const bbfd_plan *pl = b->plans[s];
     for (int k = 0; k < b->max_steps; ++k) {
@@ -983,9 +1085,23 @@ void batch_walks(const bbfd_batch *b, char *ws, int k, BatchWalk *W) {
   }
 }
 
+// Blocks until every earlier enqueue that reads the pinned staging has run.
+int wait_staging(bbfd_batch *b) {
+  if (!b->staged) return BBFD_OK;
+  hipError_t e = hipEventSynchronize(b->staged);
+  return e == hipSuccess ? BBFD_OK : hip_fail(e, "staging wait");
+}
+
+int mark_staging(bbfd_batch *b, hipStream_t s) {
+  hipError_t e = hipEventRecord(b->staged, s);
+  return e == hipSuccess ? BBFD_OK : hip_fail(e, "staging event record");
+}
+
 int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
                   float *const *peak, char *ws, hipStream_t s, int steps = -1) {
   const size_t n = b->plans.size();
+  // callers have waited for the staging (drop_graph precedes every capture and
+  // every tuning pass)
   for (size_t q = 0; q < n; ++q)
     b->h_desc[q] = step_args(b->plans[q], mat[q], src[q], peak[q], ws + b->sub_off[q]);
   std::copy(b->tiles.begin(), b->tiles.end(), b->h_tiles);
@@ -1031,6 +1147,7 @@ int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *
 }
 
 void drop_graph(bbfd_batch *b) {
+  (void)wait_staging(b);  // a launch of the graph may still be queued
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   b->key.clear();
@@ -1097,6 +1214,7 @@ void bbfd_batch_destroy(bbfd_batch *b) {
   if (!b) return;
   drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->staged) (void)hipEventDestroy(b->staged);
   if (b->h_desc) (void)hipHostFree(b->h_desc);
   if (b->h_tiles) (void)hipHostFree(b->h_tiles);
   if (b->h_coef) (void)hipHostFree(b->h_coef);
@@ -1193,7 +1311,7 @@ int bbfd_batch_solve(bbfd_batch *b, const uint8_t *const *mat, const float *cons
   }
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "graph launch");
-  return BBFD_OK;
+  return mark_staging(b, (hipStream_t)stream);
 }
 
 int bbfd_batch_status(const bbfd_batch *b, const void *workspace, int32_t i, int64_t *peak_index,
@@ -1246,7 +1364,9 @@ int bbfd_batch_autotune(bbfd_batch *b, const uint8_t *const *mat, const float *c
         }
         std::lock_guard<std::mutex> lock(b->mu);
         // warm-up pass (prologue + probe steps), then the timed probe steps
-        if ((rc = enqueue_batch(b, mat, src, peak, (char *)workspace, s, probe_steps))) goto done;
+        if ((rc = enqueue_batch(b, mat, src, peak, (char *)workspace, s, probe_steps)) ||
+            (rc = mark_staging(b, s)))
+          goto done;
         (void)hipEventRecord(e0, s);
         for (int k = 0; k < probe_steps; ++k) {
           BatchWalk W[2];

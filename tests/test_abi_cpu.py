@@ -138,3 +138,4 @@ def test_batch_rejects_empty_and_names_the_bad_problem():
     probs[2].pml = 40                  # thicker than the grid allows
     assert bb.lib().bbfd_batch_create(probs, 3, C.byref(h)) == bb.EINVAL and not h.value
     assert bb.lib().bbfd_last_error().decode().startswith("problem 2:")
+

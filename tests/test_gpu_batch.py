@@ -7,8 +7,11 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2301_12727_amd as bb
 import synth
+
+from ._parity import assert_map_matches
 
 pytestmark = pytest.mark.gpu
 
@@ -96,3 +99,71 @@ def test_batch_reports_per_solve_errors():
     with pytest.raises(bb.BBFDError) as e:
         b.status(ws, 1)
     assert e.value.code == bb.EINDEX
+
+
+def test_batched_maps_match_oracle():
+    """Every solve of the uneven five-solve batch (sizes 24-44, 250/500/700
+    kHz, 30-98 steps) against the FP64 oracle, to the single-solve bar."""
+    cases = uneven_cases()
+    b = bb.Batch(cases)
+    ws = b.workspace()
+    mats, srcs, peaks = batch_inputs(b, cases, ws)
+    b.solve(mats, srcs, peaks, ws)
+    for i, c in enumerate(cases):
+        idx, _ = b.status(ws, i)
+        ref, ridx, _ = oracle.solve_case(c)
+        assert_map_matches(peaks[i].cpu().numpy(), ref, idx, ridx, c.pml, f"batch solve {i}")
+
+
+def test_sweep_generator_cases_against_oracle():
+    """Three solves of the sweep generator (96-160 cells per axis, tilted
+    bowls, 250/500/700 kHz, skull shells at each solve's own dx) in one batch,
+    each against the FP64 oracle.  Step counts are cut to 150/190/230 (still
+    uneven) so the oracle finishes in seconds; by then the wave has crossed
+    the near skull wall in every solve."""
+    cases = synth.batch_cases(n=3)
+    for s, c in enumerate(cases):
+        c.n_steps = 150 + 40 * s
+    say_sizes = ", ".join(f"{c.nx}x{c.ny}x{c.nz}@{c.freq_hz / 1e3:.0f}kHz/{c.n_steps}" for c in cases)
+    say(f"[batch] sweep cases {say_sizes}")
+    b = bb.Batch(cases)
+    ws = b.workspace()
+    mats, srcs, peaks = batch_inputs(b, cases, ws)
+    b.solve(mats, srcs, peaks, ws)
+    for i, c in enumerate(cases):
+        idx, _ = b.status(ws, i)
+        ref, ridx, secs = oracle.solve_case(c)
+        say(f"[batch] oracle solve {i}: {secs:.1f} s")
+        assert_map_matches(peaks[i].cpu().numpy(), ref, idx, ridx, c.pml, f"sweep solve {i}")
+
+
+def test_back_to_back_batches_keep_their_own_pointers():
+    """Two batched solves of the same batch with different output buffers,
+    enqueued back to back without a synchronisation in between (the second
+    one captures a new graph while the first may still be queued): each map
+    equals the single-solve result.  Guards the host staging that the
+    captured table uploads read."""
+    cases = uneven_cases()[:3]
+    single = []
+    for c in cases:
+        P, idx, val, _ = bb.run_case(c)
+        single.append((P.cpu().numpy(), idx, val))
+    b = bb.Batch(cases)
+    ws_a = b.workspace()
+    ws_b = b.workspace()
+    mats, srcs, peaks_a = batch_inputs(b, cases, ws_a)
+    peaks_b = [torch.empty_like(p) for p in peaks_a]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    # a long queue ahead of both so the first graph is still pending when the
+    # second pointer set is staged
+    big = torch.empty(1 << 26, device="cuda")
+    for _ in range(20):
+        big.mul_(1.0)
+    b.solve(mats, srcs, peaks_a, ws_a, stream=stream)
+    b.solve(mats, srcs, peaks_b, ws_b, stream=stream)
+    for i in range(len(cases)):
+        for ws, peaks, tag in ((ws_a, peaks_a, "a"), (ws_b, peaks_b, "b")):
+            idx, val = b.status(ws, i)
+            assert_same_map(peaks[i].cpu().numpy(), single[i][0], idx, val, single[i][1],
+                            single[i][2], (tag, i))

@@ -519,3 +519,84 @@ def test_largest_accepted_grid_against_oracle_window():
     k, j, i = np.unravel_index(idx, (NZ, NY, NX))
     assert_same_peak(int(np.ravel_multi_index((k - oz, j - oy, i - ox), ref.shape)), ridx, ref, pml)
     assert val == pytest.approx(float(win[k - oz, j - oy, i - ox]))
+
+
+def test_zero_source_peak_voxel_is_first_interior_cell():
+    """With a zero source every peak value is 0: the tie goes to the lowest
+    linear index of the interior outside the layer, cell (L, L, L), as in the
+    oracle's tie pin."""
+    case = synth.random_small_case(3, n_steps=20)
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace()
+    src = torch.zeros((case.ny, case.nx), dtype=torch.complex64, device="cuda")
+    peak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    plan.solve(torch.from_numpy(case.mat).cuda(), src, peak, ws)
+    idx, val = plan.status(ws)
+    L = case.pml
+    assert float(peak.abs().max()) == 0.0
+    assert idx == (L * case.ny + L) * case.nx + L and val == 0.0
+    ref, ridx, _ = oracle.solve(oracle.problem_from_case(case), case.mat,
+                                np.zeros((case.ny, case.nx), dtype=np.complex128))
+    assert ridx == idx
+
+
+def test_plan_alternates_pointer_sets_without_recapture():
+    """A skull-like map and its water-only companion (the paper's pair of runs
+    per target), each in its own workspace, alternate on one plan: each pointer
+    set is captured once and replayed afterwards, and every replay equals the
+    direct-launch map bit for bit."""
+    case = synth.random_small_case(5, n_steps=60)
+    plan = bb.Plan.from_case(case)
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device="cuda")
+    ws = [plan.workspace(), plan.workspace()]
+    plan.source_rayleigh(case.transducer, src, ws[0])
+    mats = [torch.from_numpy(case.mat).cuda(), torch.zeros_like(torch.from_numpy(case.mat)).cuda()]
+    peaks = [torch.empty(plan.shape, dtype=torch.float32, device="cuda") for _ in range(2)]
+    direct = []
+    for q in range(2):
+        plan.solve(mats[q], src, peaks[q], ws[q], graph=False)
+        plan.status(ws[q])
+        direct.append(peaks[q].cpu().numpy())
+    assert not np.array_equal(direct[0], direct[1])
+    before = plan.graph_captures
+    for r in range(3):
+        for q in range(2):
+            peaks[q].fill_(-1.0)
+            plan.solve(mats[q], src, peaks[q], ws[q])
+        for q in range(2):
+            plan.status(ws[q])
+            assert np.array_equal(peaks[q].cpu().numpy(), direct[q]), (r, q)
+    assert plan.graph_captures - before == 2
+
+
+@pytest.mark.timeout(900)
+def test_full_map_every_tile_kind_against_oracle():
+    """Element-by-element parity of a whole 160 x 128 x 176 skull map at 500
+    kHz (3.6 M cells, 8448 tiles: acoustic, general and deep tiles, fused
+    step, two-branch captured graph), run 1000 steps (about 43 periods, past
+    the transit of the whole depth, so the field behind the near skull wall is
+    steady), against the FP64 oracle run live: rel-L2 over the whole interior
+    and the largest single-cell deviation."""
+    case = synth.skull_case(160, 128, 176, 500e3, 6.0, 1000, seed=7, name="skull160x128x176_500kHz")
+    P, idx, val, plan = bb.run_case(case)
+    ws = plan.workspace()
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device="cuda")
+    plan.source_rayleigh(case.transducer, src, ws)
+    peak = torch.empty(plan.shape, dtype=torch.float32, device="cuda")
+    plan.solve(torch.from_numpy(case.mat).cuda(), src, peak, ws)
+    plan.status(ws)
+    counts = plan.tile_counts(ws)
+    say(f"[parity] full map: tiles (acoustic, general, deep) {counts}")
+    assert sum(counts) >= 2048 and min(counts) > 0
+    P = P.cpu().numpy()
+    assert np.array_equal(peak.cpu().numpy(), P)
+    ref, ridx, secs = oracle.solve_case(case)
+    L = case.pml
+    a, b = interior(P, L), interior(ref, L)
+    err = rel_l2(a, b)
+    dev = float(np.abs(a - b).max() / np.abs(b).max())
+    say(f"[parity] full map: oracle {secs:.1f} s, rel-L2 {err:.3e}, max |diff| / max {dev:.3e}, "
+        f"peak {idx} vs {ridx}")
+    assert err <= TOL_MAP
+    assert dev <= 1e-3
+    assert_same_peak(idx, ridx, ref, L)
