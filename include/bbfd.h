@@ -170,6 +170,23 @@ int bbfd_solve_profiled(const bbfd_plan *plan, const uint8_t *mat, const float *
                         float *peak, void *workspace, uint64_t workspace_bytes, void *stream,
                         double *ms_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+   bbfd_solve_direct with the workspace taken from a fixed device array the
+   library holds on every GPU it runs on (96 MiB per GPU, held until the
+   process ends; enough for grids up to about 64^3 with the default layer).
+   Calls no allocating routine: the material and layer tables are uploaded from
+   the plan's own host memory.  The caller still passes mat, src and peak
+   (layouts as bbfd_solve).  Every call on one GPU shares that GPU's array and
+   clears what it needs at the start, so calls that overlap on one GPU (two
+   streams, two threads) race: serialise them.  When peak_index or
+   peak_value is non-NULL the call waits for stream and returns the status as
+   bbfd_status would (BBFD_EINDEX, BBFD_EDIVERGED); otherwise it returns once
+   the solve is enqueued.  BBFD_ENOMEM, without enqueuing anything, when the
+   plan's workspace_bytes exceeds the array. */
+int bbfd_solve_static(const bbfd_plan *plan, const uint8_t *mat, const float *src_re_im,
+                      float *peak, void *stream, int64_t *peak_index, float *peak_value);
+
 /* Waits for stream, then reads the device status of the last solve in this
    workspace: BBFD_EINDEX, BBFD_EDIVERGED or BBFD_OK.  peak_index receives the
    linear index (x fastest) of the largest peak value over the interior outside

@@ -58,7 +58,7 @@ EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_segment_classes", "bbfd_tile_counts",
            "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
            "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
-           "bbfd_batch_status", "bbfd_batch_autotune", "bbfd_energy_loss"]
+           "bbfd_batch_status", "bbfd_batch_autotune", "bbfd_solve_static", "bbfd_energy_loss"]
 
 _lib = None
 
@@ -85,6 +85,8 @@ def lib():
         L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
         L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
         L.bbfd_energy_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, C.c_uint64, vp, vp]
+        L.bbfd_solve_static.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_float)]
         L.bbfd_segment_classes.argtypes = [vp, vp, vp, C.c_uint64, vp]
         L.bbfd_tile_counts.argtypes = [vp, vp, vp, vp]
         L.bbfd_last_error.restype = C.c_char_p
@@ -225,6 +227,19 @@ class Plan:
                                       C.c_void_p(_stream(stream)),
                                       out.ctypes.data_as(C.c_void_p)))
         return float(out[0]), float(out[1]), int(out[2]), float(out[3]), float(out[4])
+
+    def solve_static(self, mat, src, peak, stream=None, status=True):
+        """bbfd_solve_static: the solve with the library's fixed per-GPU device
+        array as its workspace (nothing allocated).  With status=True it waits
+        and returns (peak_index, peak_value), else returns None once enqueued."""
+        idx = C.c_int64(-1)
+        val = C.c_float(0.0)
+        _check(lib().bbfd_solve_static(self.h, C.c_void_p(mat.data_ptr()),
+                                       C.c_void_p(src.data_ptr()), C.c_void_p(peak.data_ptr()),
+                                       C.c_void_p(_stream(stream)),
+                                       C.byref(idx) if status else None,
+                                       C.byref(val) if status else None))
+        return (int(idx.value), float(val.value)) if status else None
 
     def solve_profiled(self, mat, src, peak, ws, stream=None):
         """Direct-launch solve with per-kernel HIP events on the launch stream;

@@ -858,6 +858,52 @@ int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float
   return BBFD_OK;
 }
 
+// ------------------------------------------------ solve without allocation
+// Device memory of bbfd_solve_static: one file-scope array per GPU, holding
+// the whole workspace of a solve (state, tables, classes, status).  Host code
+// never uses the array's name as an address: its device address is looked up
+// once per device (with that device current) and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)96 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(BBFD_EINVAL, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+      return hip_fail(e, "scratch symbol address");
+    if (!p || (uintptr_t)p % 256) return fail(BBFD_EHIP, "scratch array misplaced");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return BBFD_OK;
+}
+
+int bbfd_solve_static(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
+                      void *stream, int64_t *peak_index, float *peak_value) {
+  if (!pl) return fail(BBFD_EINVAL, "null plan");
+  if (!mat || !src || !peak) return fail(BBFD_EINVAL, "null device pointer");
+  if (pl->ws_bytes > kScratchBytes)
+    return fail(BBFD_ENOMEM,
+                "solve needs %llu bytes of device workspace; bbfd_solve_static holds at most %llu "
+                "(use bbfd_solve with a caller workspace)",
+                (unsigned long long)pl->ws_bytes, (unsigned long long)kScratchBytes);
+  void *ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = enqueue_solve(pl, mat, src, peak, (char *)ws, s, nullptr, nullptr, false))) return rc;
+  if (peak_index || peak_value) return bbfd_status(pl, ws, peak_index, peak_value, stream);
+  return BBFD_OK;
+}
+
 int bbfd_energy_loss(const bbfd_plan *pl, const uint8_t *mat_skull, const float *peak_skull,
                      const uint8_t *mat_water, const float *peak_water, int32_t z_m,
                      void *workspace, uint64_t bytes, void *stream, double *out) {

@@ -139,3 +139,15 @@ def test_batch_rejects_empty_and_names_the_bad_problem():
     assert bb.lib().bbfd_batch_create(probs, 3, C.byref(h)) == bb.EINVAL and not h.value
     assert bb.lib().bbfd_last_error().decode().startswith("problem 2:")
 
+
+def test_static_solve_rejects_plans_beyond_its_array():
+    """bbfd_solve_static refuses a plan whose workspace exceeds its fixed
+    per-GPU array before touching the device (no GPU needed)."""
+    plan = bb.Plan(96, 96, 96, 500e3, 6.0, 10, synth.table1(500e3)["water"])
+    assert plan.workspace_bytes > 96 << 20
+    dummy = C.c_void_p(256)
+    rc = bb.lib().bbfd_solve_static(plan.h, dummy, dummy, dummy, None, None, None)
+    assert rc == bb.ENOMEM
+    assert "bbfd_solve_static holds at most" in bb.lib().bbfd_last_error().decode()
+    small = bb.Plan(48, 48, 48, 500e3, 6.0, 10, synth.table1(500e3)["water"])
+    assert small.workspace_bytes <= 96 << 20
