@@ -49,8 +49,8 @@ def test_plane_reduction_matches_oracle_on_seeded_maps(seed, shape):
             assert got[2] == ref[2]
             assert got[0] == pytest.approx(ref[0], rel=1e-12)
             assert got[1] == pytest.approx(ref[1], rel=1e-12)
-        if tie:
-            assert ref[2] == 4
+            if tie and z < 0:
+                assert got[2] == 4
 
 
 def test_plane_outside_interior_rejected():
