@@ -284,6 +284,60 @@ int bbfd_batch_autotune(bbfd_batch *batch, const uint8_t *const *mat, const floa
                         void *stream, const char *cache_path, int32_t probe_steps,
                         double *best_ms);
 
+/* ---- Thermal step (Section 2.4): the Pennes bio-heat transfer equation
+     rho C dT/dt = div(k grad T) - w rho_b C_b (T - T_a) + Q
+   (rho_b C_b = 1050 * 3617 J m^-3 K^-1 for blood) by explicit finite
+   differences on the acoustic grid: Euler steps of dt, the 7-point Laplacian
+   with each face's conductivity the harmonic mean of its two cells', and the
+   outermost cells of the grid held at T_a (the paper's 37 degC border).  The
+   heat source is Q = 2 h alpha_l I, I = p^2 / (2 rho c_l) with p the
+   acoustic peak-pressure map, h the share of the longitudinal attenuation
+   that turns into heat (the paper uses 0.16 in skull bone) and the result
+   times intensity_scale; Q is applied times the duty cycle during the first
+   n_on steps and not at all during the n_off steps after them.  Outputs are
+   the final temperature, the maximal temperature and the CEM43 thermal dose
+     dose = sum over steps of dt/60 * R^(43 - T),  R = 0.5 at T >= 43 degC,
+            0.25 below  (minutes; T at the end of each step). */
+typedef struct {
+  double k;         /* thermal conductivity, W m^-1 K^-1 */
+  double c;         /* specific heat, J kg^-1 K^-1 */
+  double perfusion; /* blood perfusion w, s^-1 */
+  double heat_frac; /* share h of alpha_l turned into heat, in [0, 1] */
+} bbfd_thermal;
+
+typedef struct {
+  int32_t nx, ny, nz;       /* >= 3 each */
+  double dx, dt;            /* grid spacing (m) and time step (s) */
+  int32_t n_on, n_off;      /* steps with the ultrasound on, then off */
+  double duty;              /* duty cycle while on, in (0, 1] */
+  double t_body;            /* T_a: border and initial temperature, degC */
+  double intensity_scale;   /* multiplies I (e.g. to reach a requested intensity) */
+  int32_t n_materials;      /* 1..256 rows of both tables, indexed like the map */
+  const bbfd_material *acoustic; /* rho, c_l and alpha_l (Np/m) are used */
+  const bbfd_thermal *thermal;
+} bbfd_bhte_problem;
+
+typedef struct bbfd_bhte bbfd_bhte;
+
+/* Validates the problem (BBFD_EINVAL for sizes, steps, duty cycle, or a dt at
+   or above the explicit stability limit min over the table of
+   rho C / (6 k / dx^2 + w rho_b C_b); BBFD_EMATERIAL for bad properties) and
+   derives the per-material coefficients in FP64.  Tables are copied. */
+int bbfd_bhte_create(const bbfd_bhte_problem *problem, bbfd_bhte **out);
+void bbfd_bhte_destroy(bbfd_bhte *plan);
+/* Device workspace a run needs and the stability limit of dt (either may be
+   NULL). */
+int bbfd_bhte_info(const bbfd_bhte *plan, uint64_t *workspace_bytes, double *dt_max);
+/* Runs all n_on + n_off steps on stream (asynchronous).  mat (dev) uint8
+   [nz][ny][nx] indices into the tables, peak (dev) float peak-pressure map
+   (Pa) of the acoustic solve; outputs (dev, float [nz][ny][nx]): t_final and
+   t_max in degC, dose in CEM43 minutes.  workspace (dev, 256-byte aligned)
+   >= workspace_bytes.  Indices >= n_materials are not checked here (the
+   acoustic solve of the same map reports them). */
+int bbfd_bhte_run(const bbfd_bhte *plan, const uint8_t *mat, const float *peak, float *t_final,
+                  float *t_max, float *dose, void *workspace, uint64_t workspace_bytes,
+                  void *stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *bbfd_last_error(void);
 

@@ -58,7 +58,8 @@ EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_segment_classes", "bbfd_tile_counts",
            "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
            "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
-           "bbfd_batch_status", "bbfd_batch_autotune", "bbfd_solve_static", "bbfd_energy_loss"]
+           "bbfd_batch_status", "bbfd_batch_autotune", "bbfd_solve_static", "bbfd_energy_loss",
+           "bbfd_bhte_create", "bbfd_bhte_destroy", "bbfd_bhte_info", "bbfd_bhte_run"]
 
 _lib = None
 

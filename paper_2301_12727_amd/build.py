@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbbfd.so")
 
-SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip", "energy.hip", "surrogate.cpp", "nn.hip"]
+SOURCES = ["bbfd.cpp", "fdtd.hip", "rayleigh.hip", "energy.hip", "bhte.cpp", "bhte.hip",
+           "surrogate.cpp", "nn.hip"]
 # The step kernels spell out every fused multiply-add (fmaf) and must not get
 # others from the compiler: every code path then rounds a cell identically.
 EXTRA = {"fdtd.hip": ["-ffp-contract=off"]}
@@ -27,7 +28,7 @@ FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 
 
 def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(BUILD, src + ".o")
     cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)

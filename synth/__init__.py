@@ -179,6 +179,44 @@ def skull_materials(freq_hz: float) -> np.ndarray:
     return _rows(*rows)
 
 
+# Thermal rows for the thermal step (k W/(m K), C J/(kg K), perfusion 1/s,
+# heating share h of alpha_l).  The paper gives no thermal properties; these
+# are typical literature values for brain and skull bone, and the bone share
+# h = 0.16 is the paper's (Section 2.4).
+THERMAL_BRAIN = (0.51, 3630.0, 0.0095, 1.0)
+THERMAL_CORTICAL = (0.32, 1313.0, 0.0003, 0.16)
+THERMAL_TRABECULAR = (0.31, 2274.0, 0.0029, 0.16)
+
+
+def thermal_materials(freq_hz: float):
+    """Acoustic and thermal tables for the thermal step on a skull map of
+    ``skull_materials`` indices: index 0 is brain tissue (Table 1 density,
+    speed and attenuation at ``freq_hz``), 1 cortical bone, 2..9 trabecular
+    bins (thermal rows mixing trabecular bone and brain by porosity).
+    Returns (acoustic [10, 5], thermal [10, 4])."""
+    ac = skull_materials(freq_hz).copy()
+    ac[0] = table1(freq_hz)["brain"]
+    rows = [THERMAL_BRAIN, THERMAL_CORTICAL]
+    for b in range(N_PORO_BINS):
+        phi = PORO_LO + b * (PORO_HI - PORO_LO) / (N_PORO_BINS - 1)
+        rows.append(tuple((1 - phi) * t + phi * w for t, w in zip(THERMAL_TRABECULAR[:3],
+                                                                   THERMAL_BRAIN[:3])) + (0.16,))
+    return ac, np.array(rows, dtype=np.float64)
+
+
+def focus_map(shape, centre, width: float, amplitude: float, seed: int = 0,
+              floor: float = 0.05) -> np.ndarray:
+    """Synthetic peak-pressure map [nz, ny, nx] (Pa): a Gaussian focal spot of
+    the given width (cells) and amplitude at ``centre`` (k, j, i), over a
+    seeded smooth background of ``floor`` times the amplitude."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (k - centre[0]) ** 2 + (j - centre[1]) ** 2 + (i - centre[2]) ** 2
+    bg = rng.uniform(0.5, 1.0, size=shape)
+    return (amplitude * (np.exp(-r2 / (2.0 * width ** 2)) + floor * bg)).astype(np.float32)
+
+
 def bowl_pose(focus, tilt_x: float, tilt_y: float, focal: float):
     """Apex and axis of a bowl rotated by ``tilt_x`` about x then ``tilt_y``
     about y (radians) around its geometric focus."""
@@ -308,16 +346,17 @@ def batch_cases(n: int = 32, lo: int = 96, hi: int = 160, build_map: bool = True
     return cases
 
 
-def surrogate_case(seed: int, n: int = 64, build_map: bool = True) -> Case:
+def surrogate_case(seed: int, n: int = 64, build_map: bool = True, freq_hz: float | None = None) -> Case:
     """n^3 sample for the learned surrogate, batch-sweep style: frequency
     BATCH_FREQS[seed % 3], PPW 6, bowl tilts from PCG64(seed) in +-15 degrees,
     bowl aperture 0.6 x lateral extent, F#1, rim 3 mm before the source plane.
     The shell's outer surface crosses the axis 15 % of the interior depth after
     the source plane and its thickness is scaled to at most a quarter of that
-    depth, so the focus lies beyond the skull at every frequency."""
+    depth, so the focus lies beyond the skull at every frequency.  ``freq_hz``
+    overrides the frequency (e.g. an out-of-distribution case)."""
     rng = np.random.default_rng(seed)
     tx, ty = (float(v) for v in rng.uniform(-15.0, 15.0, size=2))
-    f = BATCH_FREQS[seed % 3]
+    f = BATCH_FREQS[seed % 3] if freq_hz is None else float(freq_hz)
     ppw = 6.0
     dx = C_WATER / (f * ppw)
     pml = 8
