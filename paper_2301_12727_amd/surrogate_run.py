@@ -243,6 +243,58 @@ class Gate:
         return all(self.lo[k] <= st[k] <= self.hi[k] for k in self.lo)
 
 
+class Predictor:
+    """Surrogate with the FDTD solve as fallback: a case the gate accepts (and
+    whose grid is the network's n^3) is answered by the network (free field by
+    the Rayleigh integral over the grid, features, forward pass, peak map =
+    free-field peak x exp(prediction)); any other case is solved by FDTD
+    (bbfd_solve).  Calls return (peak map [nz, ny, nx] on the device, "surrogate"
+    or "fdtd")."""
+
+    def __init__(self, model, params, gate: Gate, device="cuda"):
+        self.model, self.params, self.gate, self.device = model, params, gate, device
+        self.n = model.n
+        self.counts = {"surrogate": 0, "fdtd": 0}
+
+    def _table(self, case):
+        import torch
+        synth = _synth()
+        tb = np.zeros((case.materials.shape[0], 2), dtype=np.float32)
+        tb[:, 0] = case.materials[:, 1] / synth.C_WATER - 1.0
+        tb[:, 1] = case.materials[:, 0] / synth.RHO_WATER - 1.0
+        return torch.from_numpy(tb).to(self.device)
+
+    def route(self, case) -> str:
+        n = self.n
+        fits = (case.nx, case.ny, case.nz) == (n, n, n)
+        return "surrogate" if fits and self.gate.accepts(ood_stats(case)) else "fdtd"
+
+    def __call__(self, case):
+        import torch
+        plan = bb.Plan.from_case(case)
+        ws = plan.workspace(self.device)
+        mat = torch.from_numpy(np.ascontiguousarray(case.mat)).to(self.device)
+        path = self.route(case)
+        if path == "surrogate":
+            n = self.n
+            free = torch.empty((n, n, n), dtype=torch.complex64, device=self.device)
+            plan.rayleigh_volume(case.transducer, free, ws)
+            x = torch.empty((1, 4, n, n, n), dtype=torch.float32, device=self.device)
+            sg.features(mat, self._table(case), free, x[0])
+            y = self.model.forward(self.params, x)
+            L = case.pml
+            pref = free.abs()[L:n - L, L:n - L, L:n - L].max()
+            peak = pref * torch.exp(y[0, 0])
+        else:
+            src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=self.device)
+            plan.source_rayleigh(case.transducer, src, ws)
+            peak = torch.empty(plan.shape, dtype=torch.float32, device=self.device)
+            plan.solve(mat, src, peak, ws)
+            plan.status(ws)
+        self.counts[path] += 1
+        return peak, path
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
