@@ -350,6 +350,61 @@ def energy_loss_section(bb, torch, repeats: int = 3) -> dict:
             "reduction_ms_with_sync": round(t_red * 1e3, 4), "graph_captures": caps}
 
 
+BHTE_BYTES_PER_CELL_UPDATE = 29   # theta in/out, Q, material byte, max and dose in/out
+
+
+def thermal_section(bb, torch, repeats: int = 3) -> dict:
+    """Thermal step (BHTE) on the 200x200x280 skull at 500 kHz: the acoustic
+    peak map of the transcranial solve, scaled so that the brain's spatial-peak
+    intensity is the paper's default 5 W/cm^2, heats for 40 s at 30 % duty
+    cycle and cools for 20 s (dt = 0.1 s, 600 steps).  Reports Gcell-updates/s
+    of the thermal loop (median of ``repeats``) and its HBM rate at 29 B per
+    cell update."""
+    import numpy as np
+    import synth
+    from paper_2301_12727_amd.thermal import Thermal
+    case = synth.skull200()
+    dev = torch.device("cuda:0")
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace(dev)
+    src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=dev)
+    plan.source_rayleigh(case.transducer, src, ws)
+    mat = torch.from_numpy(case.mat).to(dev)
+    peak = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+    plan.solve(mat, src, peak, ws)
+    plan.status(ws)
+    del ws
+    ac, th = synth.thermal_materials(case.freq_hz)
+    brain = torch.from_numpy(np.ascontiguousarray(case.mat == 0)).to(dev)
+    L = case.pml
+    brain[:L + 30] = False          # beyond the near skull wall
+    inten = peak.double() ** 2 / (2.0 * ac[0, 0] * ac[0, 1])
+    scale = 5e4 / float(torch.where(brain, inten, torch.zeros_like(inten)).max())
+    n_on, n_off, dt = 400, 200, 0.1
+    tp = Thermal(plan.shape, case.dx, dt, ac, th, n_on, n_off, duty=0.3, intensity_scale=scale)
+    tws = tp.workspace(dev)
+    outs = [torch.empty(plan.shape, dtype=torch.float32, device=dev) for _ in range(3)]
+    tp.run(mat, peak, *outs, tws)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        tp.run(mat, peak, *outs, tws)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    updates = case.cells * (n_on + n_off)
+    g = updates / t / 1e9
+    t_max, dose = float(outs[1].max()), float(outs[2].max())
+    log(f"[bench] BHTE {t:.3f} s: {g:.1f} Gcell-updates/s, T_max {t_max:.2f} C, dose {dose:.3g} min")
+    return {"workload": f"{case.name} thermal, {n_on}+{n_off} steps of {dt} s, duty 0.3, "
+                        f"I_SPPA-brain 5 W/cm^2",
+            "gcell_updates_per_s": round(g, 2), "seconds": round(t, 4),
+            "hbm_gbs_at_29B": round(g * BHTE_BYTES_PER_CELL_UPDATE, 1),
+            "frac_of_8TBs": round(g * BHTE_BYTES_PER_CELL_UPDATE / HBM_PEAK_GBS, 4),
+            "t_max_c": round(t_max, 3), "dose_max_min": dose, "intensity_scale": scale}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,6 +532,8 @@ def main():
     out["batched"] = None if args.no_batch else batched_section(bb, torch)
     torch.cuda.empty_cache()
     out["energy_loss"] = None if args.no_batch else energy_loss_section(bb, torch)
+    torch.cuda.empty_cache()
+    out["thermal"] = None if args.no_batch else thermal_section(bb, torch)
     torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
