@@ -121,7 +121,7 @@ def tile_kinds(case, info, classes):
     return kind
 
 
-def algorithmic_bytes(case, info, classes) -> dict:
+def algorithmic_bytes(case, info, classes, capture_share=None) -> dict:
     """Bytes each step kernel must move per launch at perfect on-chip reuse
     (FP32 state, 1-byte index), averaged over the time loop.  ``classes`` is
     the library's row-segment class map: cells of class > 0 are acoustic (one
@@ -157,7 +157,8 @@ def algorithmic_bytes(case, info, classes) -> dict:
         sl = [slice(None)] * 3
         sl[a] = np.r_[0:L, n - L:n]
         axes_in_layer[tuple(sl)] += 1
-    cap = (case.n_steps - info["capture_start"]) / case.n_steps
+    cap = ((case.n_steps - info["capture_start"]) / case.n_steps if capture_share is None
+           else capture_share)
     out = {}
     for name, mask in (("ac", cell_kind == 1), ("gen", cell_kind == 0)):
         fl = fluid & mask
@@ -350,6 +351,113 @@ def energy_loss_section(bb, torch, repeats: int = 3) -> dict:
             "reduction_ms_with_sync": round(t_red * 1e3, 4), "graph_captures": caps}
 
 
+def ct12_section(bb, torch, repeats: int = 3) -> dict:
+    """The 200x200x280 skull at 500 kHz as a 12-bit CT map (uint16 indices into
+    4096 rows, the general kernels reading the table through the caches)
+    against the same grid with the 10-row 8-bit table: Gcell-updates/s of each
+    (median of ``repeats`` captured solves), and a q_c sweep (0.4, 1, 2, 3, 4)
+    of the 8-bit map as one batch against the same five solves one by one."""
+    import numpy as np
+    import synth
+    dev = torch.device("cuda:0")
+    base = synth.skull200()
+    out = {}
+    for name, case in (("u8", base), ("u16_ct12", synth.ct_case(base, 1))):
+        plan = bb.Plan.from_case(case)
+        ws = plan.workspace(dev)
+        src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=dev)
+        plan.source_rayleigh(case.transducer, src, ws)
+        mat = torch.from_numpy(case.mat).to(dev)
+        peak = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+        plan.solve(mat, src, peak, ws)
+        plan.status(ws)
+        ts = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.solve(mat, src, peak, ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        out[name] = {"gcell_updates_per_s": round(case.cells * case.n_steps / t / 1e9, 2),
+                     "levels_in_map": int(len(np.unique(case.mat))),
+                     "table_rows": int(case.materials.shape[0])}
+        del ws, peak
+        torch.cuda.empty_cache()
+    qcs = (0.4, 1.0, 2.0, 3.0, 4.0)
+    cases = [synth.Case(**{**base.__dict__, "qc": q, "name": f"qc{q}"}) for q in qcs]
+    b = bb.Batch(cases)
+    ws = b.workspace(dev)
+    mat = torch.from_numpy(base.mat).to(dev)
+    srcs = [torch.empty((base.ny, base.nx), dtype=torch.complex64, device=dev) for _ in cases]
+    peaks = [torch.empty((base.nz, base.ny, base.nx), dtype=torch.float32, device=dev)
+             for _ in cases]
+    for i, c in enumerate(cases):
+        b.source_rayleigh(i, c.transducer, srcs[i], ws)
+    b.solve([mat] * len(cases), srcs, peaks, ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.solve([mat] * len(cases), srcs, peaks, ws)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    del ws
+    torch.cuda.empty_cache()
+    plans = [bb.Plan.from_case(c) for c in cases]
+    wss = [p.workspace(dev) for p in plans[:1]]
+    seq = torch.empty_like(peaks[0])
+    for p in plans:
+        p.solve(mat, srcs[0], seq, wss[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in plans:
+        p.solve(mat, srcs[0], seq, wss[0])
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    out["qc_sweep"] = {"qc": list(qcs), "batched_s": round(t_b, 4), "sequential_s": round(t_s, 4),
+                       "speedup": round(t_s / t_b, 3)}
+    log(f"[bench] ct12 {out['u16_ct12']['gcell_updates_per_s']} vs u8 {out['u8']['gcell_updates_per_s']} "
+        f"Gcell/s; qc sweep batched {t_b:.3f} s vs {t_s:.3f} s")
+    return out
+
+
+def array_section(bb, torch) -> dict:
+    """Refocusing a 128-element cap array through the 200x200x280 skull at 500
+    kHz (time reversal: a 3000-step point-source solve recording the source
+    plane, back-propagation to the elements), then the forward field of the
+    refocused and of the geometrically steered drives; reports the times and
+    the pressure each puts on the target."""
+    import numpy as np
+    import synth
+    dev = torch.device("cuda:0")
+    case = synth.skull200()
+    rows, cell = synth.array_for_case(case, 128)
+    plan = bb.Plan.from_case(case)
+    ws = plan.workspace(dev)
+    mat = torch.from_numpy(case.mat).to(dev)
+    peak = torch.empty(plan.shape, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w_tr, _ = plan.array_refocus(mat, rows, cell, peak, ws)
+    t_ref = time.perf_counter() - t0
+    i, j, k = cell
+    res = {"elements": len(rows), "target_cell": list(cell), "refocus_s": round(t_ref, 4)}
+    for name, w in (("steered", plan.array_steer(rows, np.array(cell) * case.dx)),
+                    ("refocused", w_tr)):
+        drv = np.array(rows)
+        drv[:, 7], drv[:, 8] = w.real, w.imag
+        src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.array_rayleigh(drv, src, ws)
+        plan.solve(mat, src, peak, ws, graph=False)
+        plan.status(ws)
+        res[f"{name}_forward_s"] = round(time.perf_counter() - t0, 4)
+        res[f"{name}_target_pa"] = float(peak[k, j, i])
+    res["gain"] = round(res["refocused_target_pa"] / res["steered_target_pa"], 4)
+    log(f"[bench] array refocus {t_ref:.3f} s; target gain {res['gain']}")
+    return res
+
+
 BHTE_BYTES_PER_CELL_UPDATE = 29   # theta in/out, Q, material byte, max and dose in/out
 
 
@@ -416,6 +524,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-sweep section")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="override the workload's time-step count (short profiling runs)")
+    ap.add_argument("--capture-start", type=int, default=None,
+                    help="override the first captured step (counter runs: n_steps leaves one "
+                         "capture launch, so the per-dispatch medians are capture-free)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -441,13 +552,26 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
+        # a second, independent calibration: a read-only reduction of the same 1 GiB
+        tot = a.sum()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            tot = a.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_r = e0.elapsed_time(e1) / 5
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "repeats": 6,
-                          "copy_ms": round(ms, 4), "copy_gbs": round(8 * n / ms / 1e6, 1)}))
+                          "copy_ms": round(ms, 4), "copy_gbs": round(8 * n / ms / 1e6, 1),
+                          "sum_bytes_read": 4 * n, "sum_ms": round(ms_r, 4),
+                          "sum_gbs": round(4 * n / ms_r / 1e6, 1), "sum": float(tot)}))
         return
 
     case = WORKLOADS[args.workload]()
     if args.time_steps:
         case.n_steps = args.time_steps
+    if args.capture_start is not None:
+        case.capture_start = args.capture_start
     log(f"[bench] workload {case.name}: {case.nx}x{case.ny}x{case.nz}, {case.n_steps} steps")
     plan = bb.Plan.from_case(case)
     info = plan.info
@@ -492,8 +616,13 @@ def main():
     achieved = ab[dom] / (avg[dom] * 1e-3) / 1e9
     log("[bench] kernel avg ms: " + ", ".join(f"{k} {avg[k]:.4f}" for k in KERNELS))
     traffic = load_traffic(dom, case.name)
+    # measured traffic comes from capture-free launches: compare it with the
+    # algorithmic bytes of a capture-free launch
+    ab0 = algorithmic_bytes(case, info, classes, capture_share=0.0)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_capture_free_launch": int(ab0[dom]),
+            "traffic_over_algorithmic": (round(traffic / ab0[dom], 3) if traffic else None),
             "kernel": f"k_{dom}", "avg_launch_ms": round(avg[dom], 5),
             "algorithmic_bytes_per_launch": int(ab[dom]),
             "kernels": {f"k_{k}": {"avg_launch_ms": round(avg[k], 5),
@@ -534,6 +663,10 @@ def main():
     out["energy_loss"] = None if args.no_batch else energy_loss_section(bb, torch)
     torch.cuda.empty_cache()
     out["thermal"] = None if args.no_batch else thermal_section(bb, torch)
+    torch.cuda.empty_cache()
+    out["ct12"] = None if args.no_batch else ct12_section(bb, torch)
+    torch.cuda.empty_cache()
+    out["phased_array"] = None if args.no_batch else array_section(bb, torch)
     torch.cuda.empty_cache()
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")

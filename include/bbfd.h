@@ -53,13 +53,19 @@ typedef struct {
    capture_start: first step whose end state enters the peak map
                   (< 0: n_steps - 2 periods).
    source_k: plane of the soft stress source (< 0: pml, the first interior
-             plane).  The property table is copied at plan creation. */
+             plane).  The property table is copied at plan creation.
+   index_bits: 8 (or 0): the material map is uint8 and the table has up to 256
+             rows; 16: the map is uint16 and the table has up to 4096 rows (CT
+             values quantised at 12 bits, Section 2.2.2).  With 16-bit maps the
+             general kernels read the table through the caches instead of LDS,
+             and only fluids of index below 255 take the acoustic kernels. */
 typedef struct {
   int32_t nx, ny, nz, pml;
   double freq_hz, ppw, qc, cfl_safety;
   int32_t n_steps, capture_start, source_k;
-  int32_t n_materials; /* 1..256 */
+  int32_t n_materials; /* 1..256 (8-bit maps) or 1..4096 (16-bit maps) */
   const bbfd_material *materials;
+  int32_t index_bits;  /* 8 (0 = 8) or 16 */
 } bbfd_problem;
 
 /* Single-element transducer (Section 2, "Single").  kind 0: flat piston,
@@ -124,11 +130,55 @@ int bbfd_source_rayleigh(const bbfd_plan *plan, const bbfd_transducer *t, float 
 int bbfd_rayleigh_volume(const bbfd_plan *plan, const bbfd_transducer *t, float *field,
                          void *workspace, uint64_t workspace_bytes, void *stream);
 
+/* ---- Phased arrays (Section 2: the multi-element transducers, with
+   electronic steering and, for refocusing, a point source at the target
+   back-propagated to the domain interface and then by Rayleigh-Sommerfeld to
+   the elements, Section 2.3).  An element is a flat circular piston driven
+   with a complex normal velocity; its surface is decomposed like the single
+   piston (rings no wider than lambda/4, equal parts of at most lambda^2/16),
+   every part carrying the element's drive. */
+typedef struct {
+  double radius_m;     /* face radius */
+  double centre_m[3];  /* face centre */
+  double axis[3];      /* radiating direction (normalised by the library) */
+  double w_re, w_im;   /* drive: normal surface velocity u e^{i phi}, m/s */
+} bbfd_element;
+
+/* Sub-element decomposition of n elements: up to cap rows of
+   (x, y, z, area, w_re, w_im) into host memory out (may be NULL to count);
+   *n_out receives the number of sub-elements. */
+int bbfd_array_elements(const bbfd_plan *plan, const bbfd_element *elements, int32_t n, double *out,
+                        int64_t cap, int64_t *n_out);
+/* Rayleigh-Sommerfeld field of the driven array on the source plane, as
+   bbfd_source_rayleigh (same layout, staging, blocking and geometry check):
+     S(x) = (i omega rho_w / 2 pi) sum_parts w_e A exp(-i k R) / R. */
+int bbfd_array_rayleigh(const bbfd_plan *plan, const bbfd_element *elements, int32_t n,
+                        float *src_re_im, void *workspace, uint64_t workspace_bytes, void *stream);
+/* Electronic steering in water to target (host, m): unit drives with phase
+   k |c_e - target| (c_e the element centre), so that every element's wave
+   arrives at the target in phase.  w (host) receives 2 n doubles (re, im). */
+int bbfd_array_steer(const bbfd_plan *plan, const bbfd_element *elements, int32_t n,
+                     const double *target, double *w);
+/* Refocusing through the map (time reversal).  (1) A solve of mat with a unit
+   force on the v_z face of the target cell (i, j, k) (k beyond the source
+   plane, inside the interior) in place of the transducer source, recording the
+   complex phasor of v_z on the faces of the source plane over the last period,
+   (2/N_T) sum v_z exp(-i omega t_n), t_n = (n + 1/2) dt; (2) the Rayleigh
+   integral of that plane (normal velocity, cells of area dx^2 at
+   z = (source_k + 1/2) dx) to every element centre, p_e; (3) the drives
+   w_e = conj(p_e) / |p_e| (host, 2 n doubles).  field (host, may be NULL)
+   receives the p_e.  peak (dev) receives the point-source solve's peak map;
+   workspace as bbfd_solve.  Synchronises stream. */
+int bbfd_array_refocus(const bbfd_plan *plan, const uint8_t *mat, const bbfd_element *elements,
+                       int32_t n, const int32_t *cell, float *peak, double *w, double *field,
+                       void *workspace, uint64_t workspace_bytes, void *stream);
+
 /* Full FDTD solve (Eq. 1 with memory variables, absorbing layer, source,
    peak capture), enqueued on stream.  The source field enters as a
    normal-traction jump of 2 S across z = (source_k + 1/2) dx (a force layer on
    the v_z faces there), ramped in over two periods.  Arguments:
-     mat (dev)        uint8 [nz][ny][nx] material indices into the table
+     mat (dev)        [nz][ny][nx] material indices into the table: uint8, or
+                      uint16 when the problem's index_bits is 16
      src_re_im (dev)  complex source plane as written by bbfd_source_rayleigh
      peak (dev)       float [nz][ny][nx], receives max |p| over the capture
                       window, p = -(sxx + syy + szz)/3
@@ -202,7 +252,8 @@ int bbfd_status(const bbfd_plan *plan, const void *workspace, int64_t *peak_inde
      I = P^2 / (2 rho c_l)   (P the peak-pressure map, rho and c_l of the
                               cell's material in the table of plan)
    with the sums over the plane's cells outside the absorbing layer.  Arguments
-   (dev, layouts as bbfd_solve, both solved with this plan's grid and table):
+   (dev, layouts and index width as bbfd_solve, both solved with this plan's
+   grid and table):
      mat_skull, peak_skull   map and peak map of the transcranial solve
      mat_water, peak_water   map (typically all water) and peak map of the
                              water-only solve
@@ -250,7 +301,10 @@ int bbfd_tile_counts(const bbfd_plan *plan, const void *workspace, int32_t *coun
 typedef struct bbfd_batch bbfd_batch;
 
 /* Creates one plan per problem (same validation and errors as
-   bbfd_plan_create, message prefixed with the problem index). */
+   bbfd_plan_create, message prefixed with the problem index); batched sweeps
+   take 8-bit maps (BBFD_EINVAL for index_bits 16).  A sweep of the
+   attenuation correction q_c (Section 3.2) over one map is a batch of problems
+   that differ only in qc. */
 int bbfd_batch_create(const bbfd_problem *problems, int32_t n, bbfd_batch **out);
 void bbfd_batch_destroy(bbfd_batch *batch);
 /* workspace_bytes: device workspace of a batched solve (all solves plus the

@@ -40,7 +40,7 @@ class Problem(C.Structure):
                 ("cfl_safety", C.c_double),
                 ("n_steps", C.c_int32), ("capture_start", C.c_int32), ("source_k", C.c_int32),
                 ("n_materials", C.c_int32), ("materials", C.POINTER(Material)),
-                ("mode", C.c_int32)]
+                ("mode", C.c_int32), ("index_bits", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -103,18 +103,23 @@ class _Prob:
     """Keeps the ctypes problem and its material array alive together."""
 
     def __init__(self, nx, ny, nz, pml, freq_hz, ppw, n_steps, materials, qc=1.0,
-                 cfl_safety=0.95, capture_start=-1, source_k=-1, mode=0):
+                 cfl_safety=0.95, capture_start=-1, source_k=-1, mode=0, index_bits=8):
         mats = np.ascontiguousarray(materials, dtype=np.float64).reshape(-1, 5)
         self.mats = (Material * len(mats))(*[Material(*map(float, r)) for r in mats])
         self.p = Problem(nx, ny, nz, pml, freq_hz, ppw, qc, cfl_safety, n_steps,
-                         capture_start, source_k, len(mats), self.mats, mode)
+                         capture_start, source_k, len(mats), self.mats, mode, index_bits)
+
+    @property
+    def map_dtype(self):
+        return np.uint16 if self.p.index_bits == 16 else np.uint8
 
 
 def problem_from_case(case, n_steps=None, mode=0, **over):
     kw = dict(nx=case.nx, ny=case.ny, nz=case.nz, pml=case.pml, freq_hz=case.freq_hz,
               ppw=case.ppw, n_steps=case.n_steps if n_steps is None else n_steps,
               materials=case.materials, qc=case.qc, cfl_safety=case.cfl_safety,
-              capture_start=case.capture_start, source_k=case.source_k, mode=mode)
+              capture_start=case.capture_start, source_k=case.source_k, mode=mode,
+              index_bits=16 if case.mat is not None and case.mat.dtype == np.uint16 else 8)
     kw.update(over)
     return _Prob(**kw)
 
@@ -134,7 +139,7 @@ class Sim:
 
     def __init__(self, prob: _Prob, mat: np.ndarray):
         self.prob = prob
-        self.mat = np.ascontiguousarray(mat, dtype=np.uint8)
+        self.mat = np.ascontiguousarray(mat, dtype=prob.map_dtype)
         self.h = C.c_void_p()
         rc = lib().bbref_sim_create(C.byref(prob.p), _ptr(self.mat), C.byref(self.h))
         if rc:
@@ -165,7 +170,7 @@ class Sim:
 
 def solve(prob: _Prob, mat: np.ndarray, src: np.ndarray):
     """Full solve; returns (peak [nz,ny,nx] float64, peak_index, loop seconds)."""
-    mat = np.ascontiguousarray(mat, dtype=np.uint8)
+    mat = np.ascontiguousarray(mat, dtype=prob.map_dtype)
     s = np.ascontiguousarray(src, dtype=np.complex128)
     peak = np.empty((prob.p.nz, prob.p.ny, prob.p.nx), dtype=np.float64)
     idx = C.c_int64(-1)

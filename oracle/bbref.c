@@ -54,7 +54,9 @@ int bbref_setup(const bbref_problem *p, bbref_info *info, bbref_matconst *mc) {
     return BBREF_EINVAL;
   if (!(p->freq_hz > 0) || !(p->ppw > 0) || !(p->qc > 0) || !(p->cfl_safety > 0))
     return BBREF_EINVAL;
-  if (p->n_materials <= 0 || p->n_materials > 256 || !p->materials) return BBREF_EINVAL;
+  if (p->index_bits != 0 && p->index_bits != 8 && p->index_bits != 16) return BBREF_EINVAL;
+  const int max_mat = p->index_bits == 16 ? 4096 : 256;
+  if (p->n_materials <= 0 || p->n_materials > max_mat || !p->materials) return BBREF_EINVAL;
   int periodic = (p->mode & BBREF_LATERAL_PERIODIC) != 0;
   if (2 * p->pml >= p->nz) return BBREF_EINVAL;
   if (!periodic && (2 * p->pml >= p->nx || 2 * p->pml >= p->ny)) return BBREF_EINVAL;
@@ -124,7 +126,7 @@ struct bbref_sim {
   bbref_info info;
   int nx, ny, nz, L, periodic, shear_src;
   size_t n;
-  uint8_t *mat;
+  uint16_t *mat; /* material index per cell (from a uint8 or uint16 map) */
   int nm;
   double *rho, *pi_u, *mu_u, *pi_tau, *mu_tau, *tau_s, *mu;
   double *f[BBREF_NFIELDS];
@@ -225,8 +227,8 @@ static double cpml(const bbref_sim *s, double *psi, size_t c, int ax, double xi,
   return d + psi[c];
 }
 
-int bbref_sim_create(const bbref_problem *p, const uint8_t *mat, bbref_sim **out) {
-  if (!out || !mat) return BBREF_EINVAL;
+int bbref_sim_create(const bbref_problem *p, const void *map, bbref_sim **out) {
+  if (!out || !map) return BBREF_EINVAL;
   *out = NULL;
   bbref_info info;
   int rc = bbref_setup(p, &info, NULL);
@@ -234,9 +236,13 @@ int bbref_sim_create(const bbref_problem *p, const uint8_t *mat, bbref_sim **out
   bbref_matconst *mc = (bbref_matconst *)calloc((size_t)p->n_materials, sizeof(bbref_matconst));
   bbref_setup(p, &info, mc);
   size_t n = (size_t)p->nx * p->ny * p->nz;
+  uint16_t *mat = (uint16_t *)malloc(n * sizeof(uint16_t));
+  for (size_t c = 0; c < n; ++c)
+    mat[c] = p->index_bits == 16 ? ((const uint16_t *)map)[c] : ((const uint8_t *)map)[c];
   for (size_t c = 0; c < n; ++c)
     if (mat[c] >= p->n_materials) {
       free(mc);
+      free(mat);
       return BBREF_EINDEX;
     }
   bbref_sim *s = (bbref_sim *)calloc(1, sizeof(bbref_sim));
@@ -246,8 +252,7 @@ int bbref_sim_create(const bbref_problem *p, const uint8_t *mat, bbref_sim **out
   s->periodic = (p->mode & BBREF_LATERAL_PERIODIC) != 0;
   s->shear_src = (p->mode & BBREF_SOURCE_SHEAR_XZ) != 0;
   s->n = n;
-  s->mat = (uint8_t *)malloc(n);
-  memcpy(s->mat, mat, n);
+  s->mat = mat;
   s->nm = p->n_materials;
   double **tabs[] = {&s->rho, &s->pi_u, &s->mu_u, &s->pi_tau, &s->mu_tau, &s->tau_s, &s->mu};
   for (int t = 0; t < 7; ++t) *tabs[t] = (double *)calloc((size_t)s->nm, sizeof(double));
@@ -457,7 +462,7 @@ static double now_s(void) {
   return ts.tv_sec + 1e-9 * ts.tv_nsec;
 }
 
-int bbref_solve(const bbref_problem *p, const uint8_t *mat, const double *src_re_im,
+int bbref_solve(const bbref_problem *p, const void *mat, const double *src_re_im,
                 double *peak, int64_t *peak_index, double *seconds) {
   bbref_sim *s = NULL;
   int rc = bbref_sim_create(p, mat, &s);

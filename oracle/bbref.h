@@ -41,6 +41,7 @@ typedef struct {
   int32_t n_materials;
   const bbref_material *materials;
   int32_t mode;
+  int32_t index_bits; /* 8 (or 0): uint8 map, <= 256 materials; 16: uint16 map, <= 4096 */
 } bbref_problem;
 
 typedef struct {
@@ -66,7 +67,7 @@ typedef struct bbref_sim bbref_sim;
 int bbref_setup(const bbref_problem *p, bbref_info *info, bbref_matconst *mc);
 
 /* Stateful stepping (fields start at zero). */
-int bbref_sim_create(const bbref_problem *p, const uint8_t *mat, bbref_sim **out);
+int bbref_sim_create(const bbref_problem *p, const void *mat, bbref_sim **out);
 void bbref_sim_destroy(bbref_sim *s);
 double *bbref_sim_field(bbref_sim *s, int32_t id); /* nz*ny*nx doubles, writable */
 /* Advance from t_n to t_{n+1}: velocity, source (force layer), stress+memory,
@@ -75,7 +76,7 @@ void bbref_sim_step(bbref_sim *s, int32_t n, const double *src_re_im);
 
 /* Whole solve: n_steps steps from rest, peak |p| map and its argmax over the
    non-absorbing interior (lowest linear index on ties). */
-int bbref_solve(const bbref_problem *p, const uint8_t *mat, const double *src_re_im,
+int bbref_solve(const bbref_problem *p, const void *mat, const double *src_re_im,
                 double *peak, int64_t *peak_index, double *seconds);
 
 /* Transducer surface elements (x, y, z, area): rings no wider than

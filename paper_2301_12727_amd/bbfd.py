@@ -35,12 +35,26 @@ class Problem(C.Structure):
                 ("freq_hz", C.c_double), ("ppw", C.c_double), ("qc", C.c_double),
                 ("cfl_safety", C.c_double),
                 ("n_steps", C.c_int32), ("capture_start", C.c_int32), ("source_k", C.c_int32),
-                ("n_materials", C.c_int32), ("materials", C.POINTER(Material))]
+                ("n_materials", C.c_int32), ("materials", C.POINTER(Material)),
+                ("index_bits", C.c_int32)]
 
 
 class Transducer(C.Structure):
     _fields_ = [("kind", C.c_int32), ("radius_m", C.c_double), ("focal_m", C.c_double),
                 ("apex_m", C.c_double * 3), ("axis", C.c_double * 3), ("u0", C.c_double)]
+
+
+class Element(C.Structure):
+    _fields_ = [("radius_m", C.c_double), ("centre_m", C.c_double * 3), ("axis", C.c_double * 3),
+                ("w_re", C.c_double), ("w_im", C.c_double)]
+
+
+def element_array(elements):
+    """ctypes array of bbfd_element from rows (radius, cx, cy, cz, ax, ay, az,
+    w_re, w_im)."""
+    rows = np.asarray(elements, dtype=np.float64).reshape(-1, 9)
+    return (Element * len(rows))(*[Element(r[0], (C.c_double * 3)(*r[1:4]),
+                                           (C.c_double * 3)(*r[4:7]), r[7], r[8]) for r in rows])
 
 
 class PlanInfo(C.Structure):
@@ -59,7 +73,8 @@ EXPORTS = ["bbfd_plan_create", "bbfd_plan_get_info", "bbfd_plan_destroy",
            "bbfd_last_error", "bbfd_rayleigh_volume", "bbfd_batch_create", "bbfd_batch_destroy", "bbfd_batch_info",
            "bbfd_batch_plan", "bbfd_batch_offset", "bbfd_batch_set_shape", "bbfd_batch_solve",
            "bbfd_batch_status", "bbfd_batch_autotune", "bbfd_solve_static", "bbfd_energy_loss",
-           "bbfd_bhte_create", "bbfd_bhte_destroy", "bbfd_bhte_info", "bbfd_bhte_run"]
+           "bbfd_bhte_create", "bbfd_bhte_destroy", "bbfd_bhte_info", "bbfd_bhte_run",
+           "bbfd_array_elements", "bbfd_array_rayleigh", "bbfd_array_steer", "bbfd_array_refocus"]
 
 _lib = None
 
@@ -85,6 +100,10 @@ def lib():
         L.bbfd_solve_direct.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp]
         L.bbfd_solve_profiled.argtypes = [vp, vp, vp, vp, vp, C.c_uint64, vp, vp]
         L.bbfd_status.argtypes = [vp, vp, C.POINTER(C.c_int64), C.POINTER(C.c_float), vp]
+        L.bbfd_array_elements.argtypes = [vp, vp, C.c_int32, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.bbfd_array_rayleigh.argtypes = [vp, vp, C.c_int32, vp, vp, C.c_uint64, vp]
+        L.bbfd_array_steer.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.bbfd_array_refocus.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, vp, vp, C.c_uint64, vp]
         L.bbfd_energy_loss.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, C.c_uint64, vp, vp]
         L.bbfd_solve_static.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_float)]
@@ -129,11 +148,12 @@ class Plan:
     """A validated problem with its derived device tables (libbbfd plan)."""
 
     def __init__(self, nx, ny, nz, freq_hz, ppw, n_steps, materials, pml=8, qc=1.0,
-                 cfl_safety=0.95, capture_start=-1, source_k=-1):
+                 cfl_safety=0.95, capture_start=-1, source_k=-1, index_bits=8):
         mats = np.ascontiguousarray(materials, dtype=np.float64).reshape(-1, 5)
         self._mats = (Material * len(mats))(*[Material(*map(float, r)) for r in mats])
         self.problem = Problem(nx, ny, nz, pml, freq_hz, ppw, qc, cfl_safety, n_steps,
-                               capture_start, source_k, len(mats), self._mats)
+                               capture_start, source_k, len(mats), self._mats, index_bits)
+        self.index_bits = index_bits
         self.h = C.c_void_p()
         _check(lib().bbfd_plan_create(C.byref(self.problem), C.byref(self.h)))
         info = PlanInfo()
@@ -148,7 +168,8 @@ class Plan:
                   n_steps=case.n_steps if n_steps is None else n_steps,
                   materials=case.materials, pml=case.pml, qc=case.qc,
                   cfl_safety=case.cfl_safety, capture_start=case.capture_start,
-                  source_k=case.source_k)
+                  source_k=case.source_k,
+                  index_bits=16 if case.mat is not None and case.mat.dtype == np.uint16 else 8)
         kw.update(over)
         return cls(**kw)
 
@@ -215,6 +236,47 @@ class Plan:
         _check(fn(self.h, C.c_void_p(mat.data_ptr()), C.c_void_p(src.data_ptr()),
                   C.c_void_p(peak.data_ptr()), C.c_void_p(ws.data_ptr()),
                   ws.numel() * ws.element_size(), C.c_void_p(_stream(stream))))
+
+    # ----------------------------------------------------------- phased arrays
+    def array_elements(self, elements) -> np.ndarray:
+        """Sub-elements [m, 6] = (x, y, z, area, w_re, w_im) of an array given as
+        rows (radius, cx, cy, cz, ax, ay, az, w_re, w_im)."""
+        el = element_array(elements)
+        n = C.c_int64(0)
+        _check(lib().bbfd_array_elements(self.h, el, len(el), None, 0, C.byref(n)))
+        out = np.empty((n.value, 6), dtype=np.float64)
+        _check(lib().bbfd_array_elements(self.h, el, len(el), out.ctypes.data_as(C.c_void_p),
+                                         n.value, C.byref(n)))
+        return out
+
+    def array_rayleigh(self, elements, src, ws, stream=None):
+        el = element_array(elements)
+        _check(lib().bbfd_array_rayleigh(self.h, el, len(el), C.c_void_p(src.data_ptr()),
+                                         C.c_void_p(ws.data_ptr()), ws.numel(),
+                                         C.c_void_p(_stream(stream))))
+
+    def array_steer(self, elements, target) -> np.ndarray:
+        """Unit complex drives focusing the array on target (m) in water."""
+        el = element_array(elements)
+        w = np.empty(2 * len(el), dtype=np.float64)
+        t = np.ascontiguousarray(target, dtype=np.float64)
+        _check(lib().bbfd_array_steer(self.h, el, len(el), t.ctypes.data_as(C.c_void_p),
+                                      w.ctypes.data_as(C.c_void_p)))
+        return w[0::2] + 1j * w[1::2]
+
+    def array_refocus(self, mat, elements, cell, peak, ws, stream=None):
+        """Time-reversal drives through mat for the target cell (i, j, k);
+        returns (drives, back-propagated field at the elements), both complex [n]."""
+        el = element_array(elements)
+        w = np.empty(2 * len(el), dtype=np.float64)
+        f = np.empty(2 * len(el), dtype=np.float64)
+        c = np.ascontiguousarray(cell, dtype=np.int32)
+        _check(lib().bbfd_array_refocus(self.h, C.c_void_p(mat.data_ptr()), el, len(el),
+                                        c.ctypes.data_as(C.c_void_p), C.c_void_p(peak.data_ptr()),
+                                        w.ctypes.data_as(C.c_void_p), f.ctypes.data_as(C.c_void_p),
+                                        C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        C.c_void_p(_stream(stream))))
+        return w[0::2] + 1j * w[1::2], f[0::2] + 1j * f[1::2]
 
     def energy_loss(self, mat_skull, peak_skull, mat_water, peak_water, ws, z_m=-1, stream=None):
         """bbfd_energy_loss: (E_L, T_S, z_m, skull plane sum, water plane sum) of

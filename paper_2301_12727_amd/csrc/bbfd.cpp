@@ -31,16 +31,24 @@ hipError_t launch_deep(const StepArgs &a, const int *const *lists, const int *co
                        hipStream_t s);
 hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tiles, int by,
                               hipStream_t s);
-hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
-                       hipStream_t s);
+hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int idx16,
+                       int *flags, hipStream_t s);
 hipError_t launch_fill(float *p, long long n, float v, hipStream_t s);
-hipError_t launch_classify(const uint8_t *idx, uint8_t *rowu, uint8_t *cls, uint8_t *keep,
-                           const Grid &g, int nseg, int kpad, const float *lut, hipStream_t s);
+hipError_t launch_classify(const uint8_t *idx, uint16_t *rowu, uint8_t *cls, uint8_t *keep,
+                           const Grid &g, int nseg, int kpad, const float *lut, int idx16,
+                           hipStream_t s);
 hipError_t launch_argmax(const float *P, int nx, int ny, int nz, int L, float *pv, long long *pi,
                          Status *st, hipStream_t s);
 int argmax_partials();
 hipError_t launch_rayleigh(const double4 *el, int n_el, int nx, int ny, int planes, double dx,
-                           double z0, double kw, double pre, float2 *out, hipStream_t s);
+                           double z0, double kw, double pre, float2 *out, hipStream_t s,
+                           const double2 *wts = nullptr);
+hipError_t launch_backprop(const float2 *plane, int nx, int ny, double dx, double zp,
+                           const double4 *pts, int n_pts, double kw, double pre, double2 *part,
+                           double2 *out, hipStream_t s);
+int backprop_partials(int n_pts);
+hipError_t launch_record_plane(const float *vz, long long base, int pitch, int nx, int ny, float c,
+                               float s, float2 *ph, hipStream_t st);
 hipError_t launch_batched_step(int by, const BatchWalk *W, const float2 *coef, const int *cap,
                                int max_steps, int n, int blocks, int max_mat, hipStream_t s);
 hipError_t launch_batch_split(const BatchTile *tiles, int n, const int *solve_end, int n_solves,
@@ -48,8 +56,8 @@ hipError_t launch_batch_split(const BatchTile *tiles, int n, const int *solve_en
                               hipStream_t s);
 hipError_t launch_plane_energy(const uint8_t *mat_s, const float *p_s, const uint8_t *mat_w,
                                const float *p_w, int nx, int ny, int L, int z_m, const Status *st,
-                               const double *inv_z, int n_mat, double2 *part, double *out,
-                               hipStream_t s);
+                               const double *inv_z, int n_mat, int idx16, double2 *part,
+                               double *out, hipStream_t s);
 int energy_out_doubles();
 int energy_partials();
 }  // namespace bbfd
@@ -120,7 +128,7 @@ struct bbfd_plan {
   int kpad = 4;                // bytes per class column (round_up(nz, 4) + 4)
   size_t off_status = 0, off_lut = 0, off_pml = 0, off_pv = 0, off_pi = 0, off_idx = 0,
          off_cls = 0, off_keep = 0, off_rowu = 0, off_alt = 0, off_kind = 0, off_lists = 0, off_counts = 0, off_state = 0, off_psi = 0,
-         off_energy = 0,
+         off_energy = 0, off_aux = 0,
          ws_bytes = 0;
   int n_tiles = 0;
   bool deep = false;    // some tile can be deep: the fused step is launched
@@ -157,8 +165,12 @@ int validate_and_derive(const bbfd_problem *p, bbfd_plan *pl) {
     return fail(BBFD_EINVAL, "plane too large");
   if (!(p->freq_hz > 0) || !(p->ppw > 0) || !(p->qc > 0) || !(p->cfl_safety > 0))
     return fail(BBFD_EINVAL, "frequency, ppw, qc and cfl_safety must be positive");
-  if (p->n_materials < 1 || p->n_materials > 256 || !p->materials)
-    return fail(BBFD_EINVAL, "need 1..256 materials");
+  if (p->index_bits != 0 && p->index_bits != 8 && p->index_bits != 16)
+    return fail(BBFD_EINVAL, "index_bits must be 8 or 16, not %d", p->index_bits);
+  const int max_mat = p->index_bits == 16 ? kMaxMaterials16 : kMaxMaterials;
+  if (p->n_materials < 1 || p->n_materials > max_mat || !p->materials)
+    return fail(BBFD_EINVAL, "need 1..%d materials for %d-bit maps", max_mat,
+                p->index_bits == 16 ? 16 : 8);
   pl->prob = *p;
   pl->mats.assign(p->materials, p->materials + p->n_materials);
   pl->prob.materials = pl->mats.data();
@@ -302,16 +314,18 @@ void layout(bbfd_plan *pl) {
   pl->kchunk = (int)std::max(1LL, std::min<long long>(kc, p.nz));
   size_t o = 0;
   pl->off_status = o; o += 256;
-  pl->off_lut = o; o += round_up(256 * kLutW * sizeof(float), 256);
+  const bool idx16 = p.index_bits == 16;
+  pl->off_lut = o;
+  o += round_up((size_t)(idx16 ? kMaxMaterials16 : kMaxMaterials) * kLutW * sizeof(float), 256);
   pl->off_pml = o; o += round_up(((size_t)p.nx + p.ny + p.nz) * sizeof(float4), 256);
   pl->off_pv = o; o += round_up(argmax_partials() * sizeof(float), 256);
   pl->off_pi = o; o += round_up(argmax_partials() * sizeof(long long), 256);
-  pl->off_idx = o; o += round_up((size_t)g.stride, 256);
+  pl->off_idx = o; o += round_up((size_t)g.stride * (idx16 ? 2 : 1), 256);
   pl->nseg = (p.nx + kSeg - 1) / kSeg;
   pl->kpad = (int)round_up((size_t)p.nz, 4) + 4;
   pl->off_cls = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
   pl->off_keep = o; o += round_up((size_t)pl->nseg * p.ny * pl->kpad, 256);
-  pl->off_rowu = o; o += round_up((size_t)pl->nseg * (p.ny + 4) * (p.nz + 4), 256);
+  pl->off_rowu = o; o += round_up((size_t)pl->nseg * (p.ny + 4) * (p.nz + 4) * 2, 256);
   pl->n_tiles = pl->nseg * (int)((p.ny + kRows - 1) / kRows) * ((p.nz + pl->kchunk - 1) / pl->kchunk);
   // A deep tile needs a whole x segment, a row block and a z chunk with
   // kDeepReach cells around them inside the grid and outside the layer; where
@@ -338,7 +352,10 @@ void layout(bbfd_plan *pl) {
   pl->off_counts = o; o += 256;
   // energy-loss reduction: a status block for the water map's peak voxel, the
   // result, the block partials
-  pl->off_energy = o; o += round_up(256 + 256 + (size_t)energy_partials() * 16, 256);
+  // phased-array refocusing: a point-source plane and the recorded phasor plane
+  pl->off_aux = o; o += round_up(2 * (size_t)p.nx * p.ny * sizeof(float2), 256);
+  pl->off_energy = o;
+  o += round_up(256 + 256 + (size_t)energy_partials() * 16 + (size_t)p.n_materials * 8, 256);
   pl->off_state = o; o += (size_t)kNState * g.stride * sizeof(float);
   pl->off_psi = o; o += (size_t)kNPsi * g.stride * sizeof(float);
   pl->off_alt = o; o += (size_t)kNOut * g.stride * sizeof(float);  // second buffers of v, sigma_ii
@@ -381,6 +398,7 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.nby = (pl->prob.ny + kRows - 1) / kRows;
   a.n_tiles = pl->n_tiles;
   a.deep = pl->deep ? 1 : 0;
+  a.idx16 = pl->prob.index_bits == 16 ? 1 : 0;
   return a;
 }
 
@@ -430,13 +448,14 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
   const long long cells = (long long)p.nx * p.ny * p.nz;
   if ((e = launch_fill(peak, cells, 0.f, s)) != hipSuccess) return hip_fail(e, "peak clear");
   Status *st = (Status *)(ws + pl->off_status);
-  if ((e = launch_pack(mat, (uint8_t *)(ws + pl->off_idx), pl->g, p.n_materials, &st->flags, s)) !=
-      hipSuccess)
+  const int idx16 = p.index_bits == 16 ? 1 : 0;
+  if ((e = launch_pack(mat, (uint8_t *)(ws + pl->off_idx), pl->g, p.n_materials, idx16, &st->flags,
+                       s)) != hipSuccess)
     return hip_fail(e, "index pack");
-  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint8_t *)(ws + pl->off_rowu),
+  if ((e = launch_classify((const uint8_t *)(ws + pl->off_idx), (uint16_t *)(ws + pl->off_rowu),
                            (uint8_t *)(ws + pl->off_cls),
                            (uint8_t *)(ws + pl->off_keep), pl->g, pl->nseg, pl->kpad,
-                           (const float *)(ws + pl->off_lut), s)) != hipSuccess)
+                           (const float *)(ws + pl->off_lut), idx16, s)) != hipSuccess)
     return hip_fail(e, "segment classes");
   StepArgs a = step_args(pl, mat, nullptr, peak, ws);
   int *lists[3] = {(int *)(ws + pl->off_lists), (int *)(ws + pl->off_lists) + pl->n_tiles,
@@ -472,14 +491,29 @@ hipError_t link(hipStream_t from, hipStream_t to, hipEvent_t ev) {
 // touch disjoint outputs, so running them side by side fills the tail of one
 // with blocks of the other.
 constexpr int kStepKernels = 5;
+// A solve that records, instead of capturing peaks: the source on plane ks
+// (overriding the plan's), and the complex phasor of v_z on the faces of plane
+// k_rec over the last period, (2 / N_T) sum v_z exp(-i omega t_n) with
+// t_n = (n + 1/2) dt (the time level of the velocities of step n).
+struct Record {
+  int ks;
+  int k_rec;
+  float2 *phasor;  // [ny][nx], cleared here
+};
+
 int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
                   char *ws, hipStream_t s, hipEvent_t *ev = nullptr, hipStream_t side = nullptr,
-                  bool pinned = true) {
+                  bool pinned = true, const Record *rec = nullptr) {
   const bbfd_problem &p = pl->prob;
   int rc = enqueue_prologue(pl, mat, peak, ws, s, pinned);
   if (rc) return rc;
   hipError_t e;
   StepArgs a = step_args(pl, mat, src, peak, ws);
+  if (rec) {
+    a.g.ks = rec->ks;
+    if ((e = launch_fill((float *)rec->phasor, 2LL * p.nx * p.ny, 0.f, s)) != hipSuccess)
+      return hip_fail(e, "phasor clear");
+  }
   const int *lists[3] = {(const int *)(ws + pl->off_lists),
                          (const int *)(ws + pl->off_lists) + pl->n_tiles,
                          (const int *)(ws + pl->off_lists) + 2 * (size_t)pl->n_tiles};
@@ -534,6 +568,14 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
       if (ev) (void)hipEventRecord(ev[2 * (kStepKernels * n + q) + 1], s);
     }
     for (int f = 0; f < kNOut; ++f) std::swap(cur[f], nxt[f]);
+    if (rec && n >= p.n_steps - pl->nt) {
+      const double t = (n + 0.5) * pl->dt, w = 2.0 / pl->nt;
+      if ((e = launch_record_plane(cur[VZ], pl->g.off(0, 0, rec->k_rec), pl->g.pitch, p.nx, p.ny,
+                                   (float)(w * std::cos(pl->omega * t)),
+                                   (float)(-w * std::sin(pl->omega * t)), rec->phasor, s)) !=
+          hipSuccess)
+        return hip_fail(e, "phasor record");
+    }
   }
   return enqueue_epilogue(pl, peak, ws, s);
 }
@@ -746,6 +788,166 @@ int bbfd_rayleigh_volume(const bbfd_plan *pl, const bbfd_transducer *t, float *f
                          pl->ks * pl->dx);
 }
 
+// ---------------------------------------------------------- phased arrays
+// Every element of an array is a flat circular piston decomposed like the
+// single piston (rings no wider than lambda/4, equal parts of at most
+// lambda^2/16); its sub-elements carry the element's complex drive.
+static int array_subelements(const bbfd_plan *pl, const bbfd_element *el, int32_t n,
+                             std::vector<double> &xyza, std::vector<double> &w) {
+  if (!pl) return fail(BBFD_EINVAL, "null plan");
+  if (!el || n < 1) return fail(BBFD_EINVAL, "need at least one array element");
+  xyza.clear();
+  w.clear();
+  for (int e = 0; e < n; ++e) {
+    bbfd_transducer t{};
+    t.kind = 0;
+    t.radius_m = el[e].radius_m;
+    for (int a = 0; a < 3; ++a) {
+      t.apex_m[a] = el[e].centre_m[a];
+      t.axis[a] = el[e].axis[a];
+    }
+    t.u0 = 1.0;
+    std::vector<double> sub;
+    int rc = make_elements(&t, pl->prob.freq_hz, sub);
+    if (rc) {
+      std::string msg = g_err;
+      return fail(rc, "array element %d: %s", e, msg.c_str());
+    }
+    xyza.insert(xyza.end(), sub.begin(), sub.end());
+    for (size_t q = 0; q < sub.size() / 4; ++q) {
+      w.push_back(el[e].w_re);
+      w.push_back(el[e].w_im);
+    }
+  }
+  return BBFD_OK;
+}
+
+int bbfd_array_elements(const bbfd_plan *pl, const bbfd_element *el, int32_t n, double *out,
+                        int64_t cap, int64_t *n_out) {
+  if (!n_out) return fail(BBFD_EINVAL, "null count output");
+  std::vector<double> xyza, w;
+  int rc = array_subelements(pl, el, n, xyza, w);
+  if (rc) return rc;
+  const int64_t m = (int64_t)(xyza.size() / 4);
+  *n_out = m;
+  if (out)
+    for (int64_t q = 0; q < std::min(m, cap); ++q) {
+      for (int a = 0; a < 4; ++a) out[6 * q + a] = xyza[4 * q + a];
+      out[6 * q + 4] = w[2 * q];
+      out[6 * q + 5] = w[2 * q + 1];
+    }
+  return BBFD_OK;
+}
+
+int bbfd_array_rayleigh(const bbfd_plan *pl, const bbfd_element *el, int32_t n, float *src,
+                        void *workspace, uint64_t bytes, void *stream) {
+  if (!pl || !src) return fail(BBFD_EINVAL, "null argument");
+  int rc = check_ws(pl, workspace, bytes);
+  if (rc) return rc;
+  std::vector<double> xyza, w;
+  if ((rc = array_subelements(pl, el, n, xyza, w))) return rc;
+  const size_t m = xyza.size() / 4;
+  const double zs = pl->ks * pl->dx;
+  for (size_t q = 0; q < m; ++q)
+    if (!(xyza[4 * q + 2] < zs))
+      return fail(BBFD_EGEOMETRY, "array sub-element %zu at z %.4g m is not before the source plane (%.4g m)",
+                  q, xyza[4 * q + 2], zs);
+  const size_t need = m * (sizeof(double4) + sizeof(double2));
+  if (need > (size_t)kNState * pl->g.stride * sizeof(float))
+    return fail(BBFD_ENOMEM, "too many array sub-elements (%zu) for the workspace", m);
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  double4 *del = (double4 *)(ws + pl->off_state);
+  double2 *dw = (double2 *)(ws + pl->off_state + m * sizeof(double4));
+  hipError_t e;
+  if ((e = hipMemcpyAsync(del, xyza.data(), m * sizeof(double4), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(dw, w.data(), m * sizeof(double2), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "array element upload");
+  const double kw = pl->omega / kCw, pre = pl->omega * kRhoW / (2.0 * kPi);
+  if ((e = launch_rayleigh(del, (int)m, pl->prob.nx, pl->prob.ny, 1, pl->dx, (pl->ks + 0.5) * pl->dx, kw,
+                           pre, (float2 *)src, s, dw)) != hipSuccess)
+    return hip_fail(e, "array rayleigh launch");
+  return BBFD_OK;
+}
+
+int bbfd_array_steer(const bbfd_plan *pl, const bbfd_element *el, int32_t n, const double *target,
+                     double *w) {
+  if (!pl || !el || n < 1 || !target || !w) return fail(BBFD_EINVAL, "null or empty argument");
+  const double k = pl->omega / kCw;
+  for (int e = 0; e < n; ++e) {
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a) r2 += (el[e].centre_m[a] - target[a]) * (el[e].centre_m[a] - target[a]);
+    const double ph = k * std::sqrt(r2);
+    w[2 * e] = std::cos(ph);
+    w[2 * e + 1] = std::sin(ph);
+  }
+  return BBFD_OK;
+}
+
+int bbfd_array_refocus(const bbfd_plan *cpl, const uint8_t *mat, const bbfd_element *el, int32_t n,
+                       const int32_t *cell, float *peak, double *w, double *field,
+                       void *workspace, uint64_t bytes, void *stream) {
+  int rc = check_solve_args(cpl, mat, (const float *)mat, peak, workspace, bytes);
+  if (rc) return rc;
+  if (!el || n < 1 || !cell || !w) return fail(BBFD_EINVAL, "null or empty argument");
+  bbfd_plan *pl = const_cast<bbfd_plan *>(cpl);
+  const bbfd_problem &p = pl->prob;
+  const int it = cell[0], jt = cell[1], kt = cell[2];
+  if (it < p.pml || it >= p.nx - p.pml || jt < p.pml || jt >= p.ny - p.pml || kt <= pl->ks ||
+      kt >= p.nz - p.pml)
+    return fail(BBFD_EINVAL, "target cell (%d, %d, %d) must lie in the interior beyond the source plane",
+                it, jt, kt);
+  {
+    std::lock_guard<std::mutex> lock(pl->mu);
+    if ((rc = ensure_pinned(pl))) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char *ws = (char *)workspace;
+  float2 *point = (float2 *)(ws + pl->off_aux);
+  float2 *ph = point + (size_t)p.nx * p.ny;
+  hipError_t e;
+  // a unit z force on the v_z face of the target cell
+  if ((e = launch_fill((float *)point, 2LL * p.nx * p.ny, 0.f, s)) != hipSuccess ||
+      (e = launch_fill((float *)(point + (size_t)jt * p.nx + it), 1, 1.f, s)) != hipSuccess)
+    return hip_fail(e, "point source");
+  Record rec{kt, pl->ks, ph};
+  if ((rc = enqueue_solve(pl, mat, (const float *)point, peak, ws, s, nullptr, nullptr, true, &rec)))
+    return rc;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "record solve");
+  if ((rc = bbfd_status(pl, ws, nullptr, nullptr, stream))) return rc;
+  // back-propagate the recorded plane to the element centres (Rayleigh)
+  const size_t need = (size_t)n * sizeof(double4) + (size_t)backprop_partials(n) * sizeof(double2) +
+                      (size_t)n * sizeof(double2);
+  if (need > (size_t)kNState * pl->g.stride * sizeof(float))
+    return fail(BBFD_ENOMEM, "too many array elements (%d) for the workspace", n);
+  std::vector<double> pts(4 * (size_t)n, 0.0);
+  for (int q = 0; q < n; ++q)
+    for (int a = 0; a < 3; ++a) pts[4 * q + a] = el[q].centre_m[a];
+  double4 *dpts = (double4 *)(ws + pl->off_state);
+  double2 *part = (double2 *)(dpts + n);
+  double2 *out = part + backprop_partials(n);
+  std::vector<double> pe(2 * (size_t)n);
+  const double kw = pl->omega / kCw, pre = pl->omega * kRhoW * pl->dx * pl->dx / (2.0 * kPi);
+  if ((e = hipMemcpyAsync(dpts, pts.data(), pts.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess ||
+      (e = launch_backprop(ph, p.nx, p.ny, pl->dx, (pl->ks + 0.5) * pl->dx, dpts, n, kw, pre, part, out,
+                           s)) != hipSuccess ||
+      (e = hipMemcpyAsync(pe.data(), out, pe.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "back-propagation");
+  for (int q = 0; q < n; ++q) {
+    const double re = pe[2 * q], im = pe[2 * q + 1], a = std::hypot(re, im);
+    w[2 * q] = a > 0 ? re / a : 0.0;          // phase conjugation: exp(-i arg p_e)
+    w[2 * q + 1] = a > 0 ? -im / a : 0.0;
+    if (field) {
+      field[2 * q] = re;
+      field[2 * q + 1] = im;
+    }
+  }
+  return BBFD_OK;
+}
+
 int bbfd_solve_direct(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float *peak,
                       void *workspace, uint64_t bytes, void *stream) {
   int rc = check_solve_args(cpl, mat, src, peak, workspace, bytes);
@@ -920,7 +1122,11 @@ int bbfd_energy_loss(const bbfd_plan *pl, const uint8_t *mat_skull, const float 
   Status *st = (Status *)(ws + pl->off_energy);
   double *res = (double *)(ws + pl->off_energy + 256);
   double2 *part = (double2 *)(ws + pl->off_energy + 512);
+  double *iz = (double *)(ws + pl->off_energy + 512 + (size_t)energy_partials() * 16);
   hipError_t e;
+  if ((e = hipMemcpyAsync(iz, pl->inv_z.data(), pl->inv_z.size() * sizeof(double),
+                          hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "impedance table upload");
   if (z_m < 0) {  // plane of the water-only map's peak voxel
     if ((e = launch_fill((float *)st, 256 / sizeof(float), 0.f, s)) != hipSuccess ||
         (e = launch_argmax(peak_water, p.nx, p.ny, p.nz, p.pml, (float *)(ws + pl->off_pv),
@@ -928,7 +1134,8 @@ int bbfd_energy_loss(const bbfd_plan *pl, const uint8_t *mat_skull, const float 
       return hip_fail(e, "water peak voxel");
   }
   if ((e = launch_plane_energy(mat_skull, peak_skull, mat_water, peak_water, p.nx, p.ny, p.pml, z_m,
-                               st, pl->inv_z.data(), p.n_materials, part, res, s)) != hipSuccess)
+                               st, iz, p.n_materials, p.index_bits == 16 ? 1 : 0, part, res,
+                               s)) != hipSuccess)
     return hip_fail(e, "plane energy launch");
   double h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int nd = energy_out_doubles();
@@ -1228,6 +1435,10 @@ int bbfd_batch_create(const bbfd_problem *probs, int32_t n, bbfd_batch **out) {
       return fail(rc, "problem %d: %s", s, msg.c_str());
     }
     b->plans.push_back(pl);
+    if (pl->prob.index_bits == 16) {
+      bbfd_batch_destroy(b);
+      return fail(BBFD_EINVAL, "problem %d: batched sweeps take 8-bit maps", s);
+    }
     b->max_steps = std::max(b->max_steps, pl->prob.n_steps);
     b->max_mat = std::max(b->max_mat, pl->prob.n_materials);
   }

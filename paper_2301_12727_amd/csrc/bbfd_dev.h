@@ -42,7 +42,8 @@ enum LutField {
   kLossless = 7,  // 1 for a fluid without attenuation (no shear, no memory), else 0
   kLutW = 8
 };
-constexpr int kMaxMaterials = 256;
+constexpr int kMaxMaterials = 256;      // rows of an 8-bit map's table (staged in LDS)
+constexpr int kMaxMaterials16 = 4096;   // rows of a 16-bit map's table (12-bit CT levels)
 
 // Row segments: the kernels' waves cover 64 consecutive x cells of one row.
 // A segment's class is m + 1 when every cell within two cells of it (the
@@ -72,7 +73,7 @@ struct PmlTab {
 
 struct StepArgs {
   Grid g;
-  const uint8_t *idx;     // padded, replicated ghosts
+  const uint8_t *idx;     // padded, replicated ghosts; uint8 or (idx16) uint16 entries
   const uint8_t *cls;     // segment classes, [ny][nseg][kpad]: one z column per segment
   int nseg;               // ceil(nx / kSeg)
   int kpad;               // round_up(nz, 4) + 4 bytes per class column
@@ -97,6 +98,7 @@ struct StepArgs {
   int nby;                // row blocks per plane (rows per block: kRows)
   int n_tiles;            // x segments * row blocks * z chunks
   int deep;               // 1: tiles may be classified deep (fused step launched)
+  int idx16;              // 1: 16-bit material indices (12-bit CT maps), table in global memory
 };
 
 // Rows of a single-solve tile (one wave per row).

@@ -17,11 +17,6 @@ namespace bbfd {
 constexpr int kEnThreads = 256;
 constexpr int kEnBlocks = 128;
 
-// 1 / (2 rho c) per material, FP64 (host-derived), passed by value.
-struct InvImpedance {
-  double v[kMaxMaterials];
-};
-
 struct EnergyOut {
   double e_l, t_s, z_m, num, den;
 };
@@ -30,11 +25,17 @@ __device__ __forceinline__ int energy_plane(int z_m, const Status *st, int nx, i
   return z_m >= 0 ? z_m : (int)(st->peak_index / ((long long)nx * ny));
 }
 
+__device__ __forceinline__ int map_at(const uint8_t *m, long long c, int idx16) {
+  return idx16 ? (int)reinterpret_cast<const uint16_t *>(m)[c] : (int)m[c];
+}
+
+// iz: 1 / (2 rho c_l) per material (FP64, host-derived); maps of uint8 or
+// (idx16) uint16 indices.
 __global__ void __launch_bounds__(kEnThreads)
     k_plane_energy(const uint8_t *__restrict__ mat_s, const float *__restrict__ p_s,
                    const uint8_t *__restrict__ mat_w, const float *__restrict__ p_w, int nx,
-                   int ny, int L, int z_m, const Status *st, InvImpedance iz,
-                   double2 *__restrict__ part) {
+                   int ny, int L, int z_m, const Status *st, const double *__restrict__ iz,
+                   int n_mat, int idx16, double2 *__restrict__ part) {
   __shared__ double sn[kEnThreads], sd[kEnThreads];
   const int k = energy_plane(z_m, st, nx, ny);
   const int wx = nx - 2 * L, wy = ny - 2 * L;
@@ -44,8 +45,9 @@ __global__ void __launch_bounds__(kEnThreads)
     const int i = L + q % wx, j = L + q / wx;
     const long long c = base + (long long)j * nx + i;
     const double a = p_s[c], b = p_w[c];
-    num += a * a * iz.v[mat_s[c]];
-    den += b * b * iz.v[mat_w[c]];
+    const int ms = map_at(mat_s, c, idx16), mw = map_at(mat_w, c, idx16);
+    num += a * a * (ms < n_mat ? iz[ms] : 0.0);
+    den += b * b * (mw < n_mat ? iz[mw] : 0.0);
   }
   sn[threadIdx.x] = num;
   sd[threadIdx.x] = den;
@@ -84,15 +86,13 @@ __global__ void __launch_bounds__(kEnBlocks)
   }
 }
 
-// part: kEnBlocks double2; out: one EnergyOut (device).
+// inv_z (dev): n_mat doubles; part: kEnBlocks double2; out: one EnergyOut (device).
 hipError_t launch_plane_energy(const uint8_t *mat_s, const float *p_s, const uint8_t *mat_w,
                                const float *p_w, int nx, int ny, int L, int z_m, const Status *st,
-                               const double *inv_z, int n_mat, double2 *part, double *out,
-                               hipStream_t s) {
-  InvImpedance iz{};
-  for (int m = 0; m < n_mat && m < kMaxMaterials; ++m) iz.v[m] = inv_z[m];
+                               const double *inv_z, int n_mat, int idx16, double2 *part,
+                               double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_plane_energy, dim3(kEnBlocks), dim3(kEnThreads), 0, s, mat_s, p_s, mat_w,
-                     p_w, nx, ny, L, z_m, st, iz, part);
+                     p_w, nx, ny, L, z_m, st, inv_z, n_mat, idx16, part);
   hipLaunchKernelGGL(k_plane_energy_final, dim3(1), dim3(kEnBlocks), 0, s, part, nx, ny, z_m, st,
                      reinterpret_cast<EnergyOut *>(out));
   return hipGetLastError();

@@ -135,13 +135,19 @@ __device__ __forceinline__ float cpml_b(float *psi, uint32_t off, float q, float
 #define DPB(a, o, s4) dfw(ldb(a, (o) - (s4)), ldb(a, o), ldb(a, (o) + (s4)), ldb(a, (o) + 2 * (s4)))
 #define DMB(a, o, s4) dbw(ldb(a, (o) - 2 * (s4)), ldb(a, (o) - (s4)), ldb(a, o), ldb(a, (o) + (s4)))
 
-__device__ __forceinline__ int ldi(const uint8_t *idx, uint32_t off) { return idx[off]; }
+// Material index of the cell at element offset off of the padded index map
+// (uint8 entries, or uint16 for 12-bit CT maps).
+template <typename IdxT>
+__device__ __forceinline__ int ldi(const uint8_t *idx, uint32_t off) {
+  return reinterpret_cast<const IdxT *>(idx)[off];
+}
 
 // Velocity update (Eq. 1 rows 1-3) of one tile: x segment bx (one cell per
 // lane), row j (wave-uniform), planes [k0, k1); lut is the LDS copy of the
 // material table.  On plane ks the v_z faces also receive the source force
 // (src_c Re S - src_s Im S, scaled by the face buoyancy): a normal-traction
 // jump of 2 S across z = (ks + 1/2) dx.
+template <typename IdxT = uint8_t>
 __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lut, int bx, int j,
                                               int k0, int k1, float src_c, float src_s) {
   const Grid &g = A.g;
@@ -185,7 +191,8 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
       stb(vzw, o, fmaf(b, f3, vzo));
       continue;
     }
-    const int m0 = ldi(idx, c), mx = ldi(idx, c + 1), my = ldi(idx, c + P), mz = ldi(idx, c + PL);
+    const int m0 = ldi<IdxT>(idx, c), mx = ldi<IdxT>(idx, c + 1), my = ldi<IdxT>(idx, c + P),
+              mz = ldi<IdxT>(idx, c + PL);
     float d1 = DPB(sxx, o, 4), d2 = DMB(sxy, o, P4), d3 = DMB(sxz, o, PL4);
     float e1 = DMB(sxy, o, 4), e2 = DPB(syy, o, P4), e3 = DMB(syz, o, PL4);
     float f1 = DMB(sxz, o, 4), f2 = DMB(syz, o, P4), f3 = DPB(szz, o, PL4);
@@ -248,6 +255,7 @@ __device__ __forceinline__ void edge(float &s, float &r, float e, float2 a, floa
 
 // Stress + memory update (Eq. 1 rows 4-9) and peak capture of one tile;
 // capture is this step's flag.
+template <typename IdxT = uint8_t>
 __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut, int bx, int j,
                                             int k0, int k1, int capture) {
   const Grid &g = A.g;
@@ -315,8 +323,10 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
       }
       continue;
     }
-    const int m0 = ldi(idx, c), mx = ldi(idx, c + 1), my = ldi(idx, c + P), mz = ldi(idx, c + PL);
-    const int mxy = ldi(idx, c + 1 + P), mxz = ldi(idx, c + 1 + PL), myz = ldi(idx, c + P + PL);
+    const int m0 = ldi<IdxT>(idx, c), mx = ldi<IdxT>(idx, c + 1), my = ldi<IdxT>(idx, c + P),
+              mz = ldi<IdxT>(idx, c + PL);
+    const int mxy = ldi<IdxT>(idx, c + 1 + P), mxz = ldi<IdxT>(idx, c + 1 + PL),
+              myz = ldi<IdxT>(idx, c + P + PL);
     float exx = DMB(vx, o, 4), eyy = DMB(vy, o, P4), ezz = dbw(z0, z1, z2, z3);
     float dyvx = DPB(vx, o, P4), dxvy = DPB(vy, o, 4);
     float dzvx = dfw(x0, x1, x2, x3), dxvz = DPB(vz, o, 4);
@@ -700,33 +710,48 @@ extern __shared__ __align__(16) float s_lut[];
 // into three lists (acoustic / general / deep, each in tile order); block b
 // of a launch takes list entry xcd_band(b, count) and blocks beyond the
 // list's length exit at once.
+// General kernels: the material table of an 8-bit map is staged in LDS; the
+// up to 4096 rows of a 16-bit map's table are read through the caches.
+template <typename IdxT>
 __global__ void __launch_bounds__(kSeg * kRows)
     k_velocity(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
-  stage_lut(s_lut, A.lut, A.n_mat);
-  __syncthreads();
+  const bool lds = sizeof(IdxT) == 1;
+  if (lds) {
+    stage_lut(s_lut, A.lut, A.n_mat);
+    __syncthreads();
+  }
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  velocity_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
+  velocity_tile<IdxT>(A, lds ? s_lut : A.lut, bx, by * kRows + wave_row(), k0, k1, A.src_c,
+                      A.src_s);
 }
 
+template <typename IdxT>
 __global__ void __launch_bounds__(kSeg * kRows)
     k_stress(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
-  stage_lut(s_lut, A.lut, A.n_mat);
-  __syncthreads();
+  const bool lds = sizeof(IdxT) == 1;
+  if (lds) {
+    stage_lut(s_lut, A.lut, A.n_mat);
+    __syncthreads();
+  }
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  stress_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.capture);
+  stress_tile<IdxT>(A, lds ? s_lut : A.lut, bx, by * kRows + wave_row(), k0, k1, A.capture);
 }
+
+// Rows the fluid-only kernels read: a lossless-fluid class m + 1 fits a byte,
+// so m < 255 and the first 256 rows suffice.
+__device__ __forceinline__ int fluid_rows(const StepArgs &A) { return min(A.n_mat, kMaxMaterials); }
 
 __global__ void __launch_bounds__(kSeg * kRows)
     k_velocity_ac(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
-  stage_lut(s_lut, A.lut, A.n_mat);
+  stage_lut(s_lut, A.lut, fluid_rows(A));
   __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
@@ -737,7 +762,7 @@ __global__ void __launch_bounds__(kSeg * kRows)
     k_stress_ac(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
-  stage_lut(s_lut, A.lut, A.n_mat);
+  stage_lut(s_lut, A.lut, fluid_rows(A));
   __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
@@ -748,7 +773,7 @@ __global__ void __launch_bounds__(kSeg * kRows)
     k_step_deep(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
-  stage_lut(s_lut, A.lut, A.n_mat);
+  stage_lut(s_lut, A.lut, fluid_rows(A));
   __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
@@ -783,6 +808,9 @@ constexpr int kReach = kDeepReach;
 __device__ __forceinline__ bool deep_x_ok(const Grid &g, int i0) {
   auto ok = [&](int p) { return p < 0 || p >= g.nx || !in_layer(p, g.nx, g.L); };
   return ok(i0 - 2) && ok(i0 - 1) && ok(i0 + kSeg);
+}
+__device__ __forceinline__ int idx_at(const StepArgs &A, long long off) {
+  return A.idx16 ? reinterpret_cast<const uint16_t *>(A.idx)[off] : A.idx[off];
 }
 __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
   const Grid &g = A.g;
@@ -820,8 +848,8 @@ __global__ void k_tile_kinds(StepArgs A, uint8_t *__restrict__ kind) {
       const bool xl = i0 - kReach >= 0, xr = i0 + kSeg - 1 + kReach < g.nx;
       for (int k = k0 - kReach; deep && k < k1 + kReach; ++k)
         for (int j = j0 - kReach; j < j0 + kRows + kReach; ++j)
-          if ((xl && A.idx[g.off(i0 - kReach, j, k)] != c - 1) ||
-              (xr && A.idx[g.off(i0 + kSeg - 1 + kReach, j, k)] != c - 1)) {
+          if ((xl && idx_at(A, g.off(i0 - kReach, j, k)) != c - 1) ||
+              (xr && idx_at(A, g.off(i0 + kSeg - 1 + kReach, j, k)) != c - 1)) {
             deep = false;
             break;
           }
@@ -1009,10 +1037,11 @@ __global__ void k_batch_kinds(const StepArgs *__restrict__ desc, BatchTile *__re
   }
 }
 
-// Padded uint8 index map with edge-replicated ghosts; flags out-of-range
-// indices (which are replaced by 0 so the solve stays in bounds).
+// Padded index map (uint8, or uint16 for 16-bit maps) with edge-replicated
+// ghosts; flags out-of-range indices (which are replaced by 0 so the solve
+// stays in bounds).
 __global__ void k_pack_idx(const uint8_t *__restrict__ mat, uint8_t *__restrict__ idx, Grid g,
-                           int n_mat, int *flags) {
+                           int n_mat, int idx16, int *flags) {
   const long long total = (long long)g.rows * (g.nz + 2 * kGhost) * g.pitch;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
@@ -1020,12 +1049,16 @@ __global__ void k_pack_idx(const uint8_t *__restrict__ mat, uint8_t *__restrict_
     const int i = min(max((int)(t - r * g.pitch) - kGhost, 0), g.nx - 1);
     const int j = min(max((int)(r % g.rows) - kGhost, 0), g.ny - 1);
     const int k = min(max((int)(r / g.rows) - kGhost, 0), g.nz - 1);
-    int m = mat[((long long)k * g.ny + j) * g.nx + i];
+    const long long q = ((long long)k * g.ny + j) * g.nx + i;
+    int m = idx16 ? reinterpret_cast<const uint16_t *>(mat)[q] : mat[q];
     if (m >= n_mat) {
       atomicOr(flags, kStatusIndex);
       m = 0;
     }
-    idx[kX0 - kGhost + t] = (uint8_t)m;
+    if (idx16)
+      reinterpret_cast<uint16_t *>(idx)[kX0 - kGhost + t] = (uint16_t)m;
+    else
+      idx[kX0 - kGhost + t] = (uint8_t)m;
   }
 }
 
@@ -1036,9 +1069,12 @@ __global__ void k_pack_idx(const uint8_t *__restrict__ mat, uint8_t *__restrict_
 // rows and planes on each side) and segment, the index all of the segment's
 // cells and two more on each side in x share (255 where they differ);
 // k_classify then asks the 5 x 5 rows around the segment's own row to agree.
-// Written as one z column of kpad bytes per (row, segment).
-__global__ void k_row_uniform(const uint8_t *__restrict__ idx, uint8_t *__restrict__ rowu, Grid g,
-                              int nseg) {
+// Written as one z column of kpad bytes per (row, segment).  rowu holds 16-bit
+// entries (0xffff where the cells differ) for either index width; only
+// fluids of index below 255 get a class of their own (classes are bytes).
+constexpr int kRowMixed = 0xffff;
+__global__ void k_row_uniform(const uint8_t *__restrict__ idx, uint16_t *__restrict__ rowu, Grid g,
+                              int nseg, int idx16) {
   const long long total = (long long)nseg * (g.ny + 4) * (g.nz + 4);
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
@@ -1047,15 +1083,18 @@ __global__ void k_row_uniform(const uint8_t *__restrict__ idx, uint8_t *__restri
     const int j = (int)(r % (g.ny + 4)) - kGhost, k = (int)(r / (g.ny + 4)) - kGhost;
     const int x0 = sg * kSeg;
     const int xa = x0 - kGhost, xb = min(x0 + kSeg - 1, g.nx - 1) + kGhost;
-    const uint8_t *row = idx + g.off(0, j, k);
-    const int m = row[xa];
+    const long long row = g.off(0, j, k);
+    auto at = [&](int x) {
+      return idx16 ? (int)reinterpret_cast<const uint16_t *>(idx)[row + x] : (int)idx[row + x];
+    };
+    const int m = at(xa);
     bool same = true;
-    for (int x = xa + 1; same && x <= xb; ++x) same = row[x] == m;
-    rowu[t] = same ? (uint8_t)m : (uint8_t)255;
+    for (int x = xa + 1; same && x <= xb; ++x) same = at(x) == m;
+    rowu[t] = same ? (uint16_t)m : (uint16_t)kRowMixed;
   }
 }
 
-__global__ void k_classify(const uint8_t *__restrict__ rowu, uint8_t *__restrict__ cls, Grid g,
+__global__ void k_classify(const uint16_t *__restrict__ rowu, uint8_t *__restrict__ cls, Grid g,
                            int nseg, int kpad, const float *__restrict__ lut) {
   const long long total = (long long)nseg * g.ny * g.nz;
   const long long rstride = (long long)(g.ny + 4) * nseg;  // one padded plane of rowu
@@ -1064,7 +1103,7 @@ __global__ void k_classify(const uint8_t *__restrict__ rowu, uint8_t *__restrict
     const int k = (int)(t % g.nz);
     const long long r = t / g.nz;
     const int sg = (int)(r % nseg), j = (int)(r / nseg);
-    const uint8_t *c = rowu + (long long)(k + kGhost) * rstride + (long long)(j + kGhost) * nseg + sg;
+    const uint16_t *c = rowu + (long long)(k + kGhost) * rstride + (long long)(j + kGhost) * nseg + sg;
     const int m = *c;
     bool ok = m < 255 && lut[m * kLutW + kLossless] != 0.f;
     for (int dk = -kGhost; ok && dk <= kGhost; ++dk)
@@ -1201,24 +1240,34 @@ __global__ void __launch_bounds__(kRedThreads)
 // ------------------------------------------------------------------ launchers
 
 static size_t lut_bytes(int n_mat) { return (size_t)n_mat * kLutW * sizeof(float); }
+// LDS of a launch: the whole table of an 8-bit map for the general kernels
+// (none for a 16-bit map: its table is read through the caches); the fluid
+// rows for the acoustic kernels and the fused step.
+static size_t lds_general(const StepArgs &a) { return a.idx16 ? 0 : lut_bytes(a.n_mat); }
+static size_t lds_fluid(const StepArgs &a) {
+  return lut_bytes(a.n_mat < kMaxMaterials ? a.n_mat : kMaxMaterials);
+}
 
 // lists: [0] acoustic tile ids, [1] general tile ids (n_tiles ints each);
 // counts: their lengths (device).  Each launch has n_tiles blocks.
 hipError_t launch_velocity(const StepArgs &a, const int *const *lists, const int *counts,
                            int which, hipStream_t s) {
   if (which == 0)
-    hipLaunchKernelGGL(k_velocity_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s,
-                       a, lists[0], counts);
+    hipLaunchKernelGGL(k_velocity_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_fluid(a), s, a,
+                       lists[0], counts);
+  else if (a.idx16)
+    hipLaunchKernelGGL(k_velocity<uint16_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a),
+                       s, a, lists[1], counts + 1);
   else
-    hipLaunchKernelGGL(k_velocity, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a,
-                       lists[1], counts + 1);
+    hipLaunchKernelGGL(k_velocity<uint8_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a),
+                       s, a, lists[1], counts + 1);
   return hipGetLastError();
 }
 
 // Fused step of the deep tiles (lists[2], counts[2]).
 hipError_t launch_deep(const StepArgs &a, const int *const *lists, const int *counts,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_step_deep, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a,
+  hipLaunchKernelGGL(k_step_deep, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_fluid(a), s, a,
                      lists[2], counts + 2);
   return hipGetLastError();
 }
@@ -1226,11 +1275,14 @@ hipError_t launch_deep(const StepArgs &a, const int *const *lists, const int *co
 hipError_t launch_stress(const StepArgs &a, const int *const *lists, const int *counts, int which,
                          hipStream_t s) {
   if (which == 0)
-    hipLaunchKernelGGL(k_stress_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s,
-                       a, lists[0], counts);
+    hipLaunchKernelGGL(k_stress_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_fluid(a), s, a,
+                       lists[0], counts);
+  else if (a.idx16)
+    hipLaunchKernelGGL(k_stress<uint16_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a), s,
+                       a, lists[1], counts + 1);
   else
-    hipLaunchKernelGGL(k_stress, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lut_bytes(a.n_mat), s, a,
-                       lists[1], counts + 1);
+    hipLaunchKernelGGL(k_stress<uint8_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a), s,
+                       a, lists[1], counts + 1);
   return hipGetLastError();
 }
 
@@ -1253,15 +1305,16 @@ hipError_t launch_tile_lists(const StepArgs &a, uint8_t *kind, int *const *lists
   return hipGetLastError();
 }
 
-hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int *flags,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_pack_idx, dim3(2048), dim3(256), 0, s, mat, idx, g, n_mat, flags);
+hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int idx16,
+                       int *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_idx, dim3(2048), dim3(256), 0, s, mat, idx, g, n_mat, idx16, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_classify(const uint8_t *idx, uint8_t *rowu, uint8_t *cls, uint8_t *keep,
-                           const Grid &g, int nseg, int kpad, const float *lut, hipStream_t s) {
-  hipLaunchKernelGGL(k_row_uniform, dim3(4096), dim3(256), 0, s, idx, rowu, g, nseg);
+hipError_t launch_classify(const uint8_t *idx, uint16_t *rowu, uint8_t *cls, uint8_t *keep,
+                           const Grid &g, int nseg, int kpad, const float *lut, int idx16,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_row_uniform, dim3(4096), dim3(256), 0, s, idx, rowu, g, nseg, idx16);
   hipLaunchKernelGGL(k_classify, dim3(4096), dim3(256), 0, s, rowu, cls, g, nseg, kpad, lut);
   hipLaunchKernelGGL(k_keep, dim3(4096), dim3(256), 0, s, cls, keep, g, nseg, kpad);
   return hipGetLastError();

@@ -239,6 +239,76 @@ def bowl_focus_for_standoff(zs: float, radius: float, focal: float, axis, stando
     return zs - standoff - rim_top
 
 
+# ------------------------------------------------------------ phased arrays
+
+def cap_array(focus, focal: float, aperture_radius: float, n: int, piston_radius: float,
+              rings: int = 0) -> np.ndarray:
+    """n flat circular pistons on a spherical cap of curvature radius ``focal``
+    and aperture radius ``aperture_radius`` around the axis +z through
+    ``focus``, each facing the focus; rows (radius, cx, cy, cz, ax, ay, az,
+    w_re, w_im) with unit drive.  rings = 0: centres on a golden-angle spiral
+    over the cap (a hemispherical-array layout, like the paper's multi-element
+    H317); rings > 0: ``rings`` annuli of equal area, each with n // rings
+    pistons equally spaced in azimuth (an annular-array layout, like its
+    CTX-500).  Stands in for the paper's transducers, whose geometry it does
+    not print."""
+    f = np.asarray(focus, dtype=np.float64)
+    th_max = math.asin(aperture_radius / focal)
+    # polar angles of element centres, measured from -z at the focus
+    if rings > 0:
+        per = max(1, n // rings)
+        c_edges = np.linspace(1.0, math.cos(th_max), rings + 1)      # equal-area annuli
+        th = []
+        ph = []
+        for r in range(rings):
+            t = math.acos(0.5 * (c_edges[r] + c_edges[r + 1]))
+            for q in range(per):
+                th.append(t)
+                ph.append(2 * math.pi * (q + 0.5 * (r % 2)) / per)
+        th, ph = np.array(th), np.array(ph)
+    else:
+        q = np.arange(n) + 0.5
+        th = np.arccos(1.0 - (1.0 - math.cos(th_max)) * q / n)
+        ph = q * math.pi * (3.0 - math.sqrt(5.0))
+    pos = f[None, :] + focal * np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph),
+                                         -np.cos(th)], axis=1)
+    ax = (f[None, :] - pos) / focal
+    rows = np.zeros((len(th), 9))
+    rows[:, 0] = piston_radius
+    rows[:, 1:4] = pos
+    rows[:, 4:7] = ax
+    rows[:, 7] = 1.0
+    return rows
+
+
+def array_for_case(case: "Case", elements: int = 32, rings: int = 0):
+    """A phased array for a case in place of its bowl: a cap of aperture 0.6 x
+    the smaller lateral extent, F#1, rim 3 mm (plus 0.2 wavelengths) before the
+    source plane, centred on the grid's middle column, with ``elements``
+    pistons of radius 0.2 wavelengths.  Returns (element rows, target cell
+    (i, j, k) of the geometric focus)."""
+    dx, zs = case.dx, case.source_plane_z()
+    aperture_r = 0.3 * min(case.nx, case.ny) * dx
+    focal = 2.0 * aperture_r
+    lam = C_WATER / case.freq_hz
+    fz = bowl_focus_for_standoff(zs, aperture_r, focal, (0.0, 0.0, 1.0), 3e-3 + 0.2 * lam)
+    focus = ((case.nx // 2) * dx, (case.ny // 2) * dx, fz)
+    rows = cap_array(focus, focal, aperture_r, elements, 0.2 * lam, rings)
+    return rows, (case.nx // 2, case.ny // 2, int(round(fz / dx)))
+
+
+def array_case(seed: int, n: int = 64, rings: int = 0, elements: int = 32,
+               freq_hz: float = 500e3, n_steps: int | None = None):
+    """A 64^3-style skull patch (``surrogate_case`` map at ``freq_hz``) with a
+    phased array in place of the bowl (``array_for_case``).  Returns (case,
+    element rows, target cell (i, j, k))."""
+    c = surrogate_case(seed, n, freq_hz=freq_hz)
+    if n_steps is not None:
+        c.n_steps = n_steps
+    rows, cell = array_for_case(c, elements, rings)
+    return c, rows, cell
+
+
 def skull_map(nx: int, ny: int, nz: int, dx: float, zs: float, seed: int,
               r_out: float = 70e-3, centre_depth: float = 80e-3,
               axis_ij=None, chunk: int = 16, thick_scale: float = 1.0) -> np.ndarray:
@@ -317,6 +387,63 @@ def skull400(n_steps: int = 5000, build_map: bool = True) -> Case:
     """400x400x520 skull at 700 kHz, PPW 9 (seed 4)."""
     return skull_case(400, 400, 520, 700e3, 9.0, n_steps, seed=4,
                       name="skull400x400x520_700kHz", build_map=build_map)
+
+
+# ---------------------------------------------------------- 12-bit CT maps
+
+CT_LEVELS = 4096            # 12-bit CT values (Section 2.2.2)
+CT_HU_MAX = 3000.0          # Hounsfield range quantised onto levels 1..4095
+CT_HU_CORTICAL = 2400.0     # HU of non-porous bone in the synthetic mapping
+
+
+def ct_materials(freq_hz: float) -> np.ndarray:
+    """4096-row table for 12-bit CT maps: row 0 water (brain and skin as
+    water), row l >= 1 the bone of HU = (l - 1) / 4094 * CT_HU_MAX, porosity
+    phi = 1 - HU / CT_HU_CORTICAL clipped to [0, 1], mixing cortical bone and
+    water linearly in density and longitudinal speed, shear speed scaled by
+    (1 - phi), trabecular attenuation (the mapping functions of the paper's
+    CT study are cited there, not printed; this linear porosity mapping stands
+    in for them)."""
+    t = table1(freq_hz)
+    rho_c, cl_c, cs_c, _, _ = t["cortical"]
+    _, _, _, al_t, as_t = t["trabecular"]
+    rows = [t["water"]]
+    for lvl in range(1, CT_LEVELS):
+        hu = (lvl - 1) / (CT_LEVELS - 2) * CT_HU_MAX
+        phi = min(1.0, max(0.0, 1.0 - hu / CT_HU_CORTICAL))
+        cs = (1 - phi) * cs_c
+        rows.append(((1 - phi) * rho_c + phi * RHO_WATER, (1 - phi) * cl_c + phi * C_WATER,
+                     cs, al_t, as_t if cs > 0 else 0.0))
+    return _rows(*rows)
+
+
+def ct_levels(skull: np.ndarray, dx: float, seed: int) -> np.ndarray:
+    """uint16 12-bit CT map of a skull-shell map (``skull_map`` indices): water
+    stays 0; bone cells get the level of HU = CT_HU_CORTICAL (1 - phi), with
+    porosity phi = 0.05 + 0.05 n in cortical cells and 0.4 + 0.2 n (clipped to
+    [0.15, 0.65]) in trabecular ones, n seeded value noise on a 2 mm lattice."""
+    rng = np.random.default_rng(seed + 7919)
+    nz, ny, nx = skull.shape
+    noise = _ValueNoise(rng, 2e-3, (-dx, -dx, -dx), (nx * dx, ny * dx, nz * dx))
+    out = np.zeros(skull.shape, dtype=np.uint16)
+    kk, jj, ii = np.nonzero(skull)
+    n = noise(ii * dx, jj * dx, kk * dx)
+    cort = skull[kk, jj, ii] == 1
+    phi = np.where(cort, 0.05 + 0.05 * n, np.clip(0.4 + 0.2 * n, 0.15, 0.65))
+    hu = CT_HU_CORTICAL * (1.0 - phi)
+    lvl = 1 + np.rint(hu / CT_HU_MAX * (CT_LEVELS - 2)).astype(np.int64)
+    out[kk, jj, ii] = np.clip(lvl, 1, CT_LEVELS - 1).astype(np.uint16)
+    return out
+
+
+def ct_case(base: "Case", seed: int = 0) -> "Case":
+    """The 12-bit CT version of a skull-shell case: same grid, source and step
+    count, the uint16 map of ``ct_levels`` and the 4096-row ``ct_materials``."""
+    c = dataclasses.replace(base)
+    c.name = base.name + "_ct12"
+    c.materials = ct_materials(base.freq_hz)
+    c.mat = ct_levels(base.mat, base.dx, seed)
+    return c
 
 
 BATCH_FREQS = (250e3, 500e3, 700e3)
