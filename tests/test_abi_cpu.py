@@ -151,3 +151,66 @@ def test_static_solve_rejects_plans_beyond_its_array():
     assert "bbfd_solve_static holds at most" in bb.lib().bbfd_last_error().decode()
     small = bb.Plan(48, 48, 48, 500e3, 6.0, 10, synth.table1(500e3)["water"])
     assert small.workspace_bytes <= 96 << 20
+
+
+def test_array_elements_and_steering_match_oracle():
+    """Phased-array host logic (no device call): the sub-element decomposition
+    of every piston equals the oracle's flat-piston decomposition, with the
+    element's drive attached, and the steering drives equal the oracle's."""
+    from oracle import array as ref_array
+    case, rows, cell = synth.array_case(20001, rings=4)
+    rows = rows.copy()
+    rows[:, 7], rows[:, 8] = np.cos(np.arange(len(rows))), np.sin(np.arange(len(rows)))
+    plan = bb.Plan.from_case(case)
+    sub = plan.array_elements(rows)
+    ref = np.concatenate([oracle.elements(ref_array._piston(r), case.freq_hz) for r in rows])
+    assert sub.shape == (len(ref), 6)
+    np.testing.assert_allclose(sub[:, :4], ref, rtol=1e-12, atol=1e-15)
+    per = len(ref) // len(rows)
+    np.testing.assert_array_equal(sub[:, 4], np.repeat(rows[:, 7], per))
+    T = np.array(cell) * case.dx
+    np.testing.assert_allclose(plan.array_steer(rows, T), ref_array.steer(rows, T, case.freq_hz),
+                               rtol=0, atol=1e-12)
+
+
+def test_bhte_plan_validation_and_stability_limit():
+    """Thermal plans: the reported stability limit is the oracle's over the
+    whole table; a dt at or above it and a heating share above 1 are
+    rejected."""
+    from oracle import bhte as ref_bhte
+    from paper_2301_12727_amd.thermal import Thermal
+    ac, th = synth.thermal_materials(500e3)
+    dx = 3e-4
+    plan = Thermal((20, 21, 22), dx, 0.01, ac, th, 10, 5)
+    mat_all = np.arange(len(ac), dtype=np.uint8)
+    assert plan.dt_max == pytest.approx(ref_bhte.stable_dt(mat_all, ac, th[:, :3], dx), rel=1e-12)
+    with pytest.raises(bb.BBFDError) as e:
+        Thermal((20, 21, 22), dx, plan.dt_max, ac, th, 10, 5)
+    assert e.value.code == bb.EINVAL
+    bad = th.copy()
+    bad[2, 3] = 1.2
+    with pytest.raises(bb.BBFDError) as e:
+        Thermal((20, 21, 22), dx, 0.01, ac, bad, 10, 5)
+    assert e.value.code == bb.EMATERIAL
+    with pytest.raises(bb.BBFDError) as e:
+        Thermal((20, 21, 22), dx, 0.01, ac, th, 10, 5, duty=1.5)
+    assert e.value.code == bb.EINVAL
+
+
+def test_16_bit_maps_allow_4096_rows_only_in_single_solves():
+    table = synth.ct_materials(500e3)
+    p16 = bb.Plan(40, 40, 40, 500e3, 6.0, 10, table, pml=4, index_bits=16)
+    assert p16.workspace_bytes > bb.Plan(40, 40, 40, 500e3, 6.0, 10, table[:256], pml=4).workspace_bytes
+    with pytest.raises(bb.BBFDError) as e:
+        bb.Plan(40, 40, 40, 500e3, 6.0, 10, table, pml=4)
+    assert e.value.code == bb.EINVAL
+    with pytest.raises(bb.BBFDError) as e:
+        bb.Plan(40, 40, 40, 500e3, 6.0, 10, np.vstack([table, table[:1]]), pml=4, index_bits=16)
+    assert e.value.code == bb.EINVAL
+    with pytest.raises(bb.BBFDError) as e:
+        bb.Plan(40, 40, 40, 500e3, 6.0, 10, table[:4], pml=4, index_bits=12)
+    assert e.value.code == bb.EINVAL
+    case = synth.ct_case(synth.surrogate_case(20001), 1)
+    with pytest.raises(bb.BBFDError) as e:
+        bb.Batch([case])
+    assert e.value.code == bb.EINVAL
