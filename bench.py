@@ -409,6 +409,9 @@ def ct12_section(bb, torch, repeats: int = 3) -> dict:
              for _ in cases]
     for i, c in enumerate(cases):
         b.source_rayleigh(i, c.transducer, srcs[i], ws)
+    t0 = time.perf_counter()
+    _, qshape = b.autotune([mat] * len(cases), srcs, peaks, ws, probe_steps=10)
+    t_tune = time.perf_counter() - t0
     b.solve([mat] * len(cases), srcs, peaks, ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -429,7 +432,9 @@ def ct12_section(bb, torch, repeats: int = 3) -> dict:
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
     out["qc_sweep"] = {"qc": list(qcs), "batched_s": round(t_b, 4), "sequential_s": round(t_s, 4),
-                       "speedup": round(t_s / t_b, 3)}
+                       "speedup": round(t_s / t_b, 3),
+                       "shape": dict(zip(("rows_per_block", "blocks", "kchunk", "tiles"), qshape)),
+                       "autotune_s": round(t_tune, 2)}
     log(f"[bench] ct12 {out['u16_ct12']['gcell_updates_per_s']} vs u8 {out['u8']['gcell_updates_per_s']} "
         f"Gcell/s; qc sweep batched {t_b:.3f} s vs {t_s:.3f} s")
     return out

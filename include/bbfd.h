@@ -296,7 +296,10 @@ int bbfd_tile_counts(const bbfd_plan *plan, const void *workspace, int32_t *coun
    general tiles) walk ragged per-kind (solve, tile) tables ordered by
    decreasing step count, so solves drop out of them once their own step count
    is reached; the blocks are persistent or one per tile (autotuned), and the
-   whole sweep is captured in one HIP graph.  Results equal those of the same
+   whole sweep is captured in one HIP graph.  For sweeps of solves that each
+   fill the GPU, the per-solve shape instead captures every solve's own step
+   kernels (acoustic, general and fused deep tiles, as bbfd_solve) one solve
+   after the other into the batch's graph.  Results equal those of the same
    problems solved one by one with bbfd_solve, bit for bit. */
 typedef struct bbfd_batch bbfd_batch;
 
@@ -310,7 +313,7 @@ void bbfd_batch_destroy(bbfd_batch *batch);
 /* workspace_bytes: device workspace of a batched solve (all solves plus the
    tile/descriptor tables).  shape (may be NULL, 4 ints): rows per block,
    persistent blocks (0: one block per tile), z cells per tile, number of
-   tiles. */
+   tiles; all four 0 for the per-solve shape. */
 int bbfd_batch_info(const bbfd_batch *batch, uint64_t *workspace_bytes, int32_t *shape);
 /* Plan of solve i (owned by the batch) and the byte offset of its part of the
    batch workspace, e.g. for bbfd_source_rayleigh on that solve. */
@@ -318,7 +321,8 @@ const bbfd_plan *bbfd_batch_plan(const bbfd_batch *batch, int32_t i);
 uint64_t bbfd_batch_offset(const bbfd_batch *batch, int32_t i);
 /* Launch shape: by in {1, 2, 4, 8} rows per 64-wide block; blocks >= 1
    persistent blocks, or 0 for one block per tile; kchunk >= 1 z cells per
-   tile (>= 4 when by = 1). */
+   tile (>= 4 when by = 1).  by = 0 selects the per-solve shape (blocks and
+   kchunk are then ignored).  BBFD_EINVAL for any other shape. */
 int bbfd_batch_set_shape(bbfd_batch *batch, int32_t by, int32_t blocks, int32_t kchunk);
 /* mat, src, peak: host arrays of n device pointers (layouts as bbfd_solve).
    Captures on first use per pointer set and launch shape; enqueued on stream. */
@@ -330,9 +334,10 @@ int bbfd_batch_status(const bbfd_batch *batch, const void *workspace, int32_t i,
 /* Tile-shape autotuner: if cache_path names a file holding a line for this
    sweep's size class ("gfx950:n<solves>:c<log1.01 cells>:s<max steps>"), applies
    its shape; otherwise times probe_steps batched steps for every candidate
-   shape on these inputs (synchronising stream), applies the fastest, appends
-   it to cache_path (if given) and writes its time to *best_ms.  The workspace
-   contents are overwritten. */
+   tiled shape (direct launches) and probe_steps steps of every solve in the
+   per-solve shape (one captured graph) on these inputs (synchronising
+   stream), applies the fastest, appends it to cache_path (if given) and
+   writes its time to *best_ms.  The workspace contents are overwritten. */
 int bbfd_batch_autotune(bbfd_batch *batch, const uint8_t *const *mat, const float *const *src,
                         float *const *peak, void *workspace, uint64_t workspace_bytes,
                         void *stream, const char *cache_path, int32_t probe_steps,

@@ -501,19 +501,15 @@ struct Record {
   float2 *phasor;  // [ny][nx], cleared here
 };
 
-int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
-                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr, hipStream_t side = nullptr,
-                  bool pinned = true, const Record *rec = nullptr) {
+// Steps [n0, n1) of a solve whose prologue has been enqueued (arguments as
+// enqueue_solve).
+int enqueue_steps(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
+                  char *ws, hipStream_t s, int n0, int n1, hipEvent_t *ev = nullptr,
+                  hipStream_t side = nullptr, const Record *rec = nullptr) {
   const bbfd_problem &p = pl->prob;
-  int rc = enqueue_prologue(pl, mat, peak, ws, s, pinned);
-  if (rc) return rc;
   hipError_t e;
   StepArgs a = step_args(pl, mat, src, peak, ws);
-  if (rec) {
-    a.g.ks = rec->ks;
-    if ((e = launch_fill((float *)rec->phasor, 2LL * p.nx * p.ny, 0.f, s)) != hipSuccess)
-      return hip_fail(e, "phasor clear");
-  }
+  if (rec) a.g.ks = rec->ks;
   const int *lists[3] = {(const int *)(ws + pl->off_lists),
                          (const int *)(ws + pl->off_lists) + pl->n_tiles,
                          (const int *)(ws + pl->off_lists) + 2 * (size_t)pl->n_tiles};
@@ -526,8 +522,9 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
   for (int f = 0; f < kNOut; ++f) {
     cur[f] = a.f[f];
     nxt[f] = (float *)(ws + pl->off_alt) + (size_t)f * pl->g.stride;
+    if (n0 % 2) std::swap(cur[f], nxt[f]);  // step n reads the buffers of parity n
   }
-  for (int n = 0; n < p.n_steps; ++n) {
+  for (int n = n0; n < n1; ++n) {
     a.src_c = pl->src_c[n];
     a.src_s = pl->src_s[n];
     a.capture = (n + 1 >= pl->cap) ? 1 : 0;
@@ -577,7 +574,35 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
         return hip_fail(e, "phasor record");
     }
   }
+  return BBFD_OK;
+}
+
+int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, float *peak,
+                  char *ws, hipStream_t s, hipEvent_t *ev = nullptr, hipStream_t side = nullptr,
+                  bool pinned = true, const Record *rec = nullptr) {
+  const bbfd_problem &p = pl->prob;
+  int rc = enqueue_prologue(pl, mat, peak, ws, s, pinned);
+  if (rc) return rc;
+  if (rec) {
+    hipError_t e = launch_fill((float *)rec->phasor, 2LL * p.nx * p.ny, 0.f, s);
+    if (e != hipSuccess) return hip_fail(e, "phasor clear");
+  }
+  if ((rc = enqueue_steps(pl, mat, src, peak, ws, s, 0, p.n_steps, ev, side, rec))) return rc;
   return enqueue_epilogue(pl, peak, ws, s);
+}
+
+// The second branch of captured steps (stream and fork/join events), made at
+// the first capture, under the plan's mutex.
+int ensure_branch(bbfd_plan *pl) {
+  hipError_t e;
+  if (!pl->side_stream &&
+      (e = hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e, "capture stream");
+  if (!pl->fork && (e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "capture event");
+  if (!pl->join && (e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming)) != hipSuccess)
+    return hip_fail(e, "capture event");
+  return BBFD_OK;
 }
 
 // Waits for the last launch of a cached graph, then frees it.
@@ -1014,13 +1039,7 @@ int bbfd_solve(const bbfd_plan *cpl, const uint8_t *mat, const float *src, float
     if (!pl->cap_stream &&
         (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess)
       return hip_fail(e, "capture stream");
-    if (!pl->side_stream &&
-        (e = hipStreamCreateWithFlags(&pl->side_stream, hipStreamNonBlocking)) != hipSuccess)
-      return hip_fail(e, "capture stream");
-    if (!pl->fork && (e = hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming)) != hipSuccess)
-      return hip_fail(e, "capture event");
-    if (!pl->join && (e = hipEventCreateWithFlags(&pl->join, hipEventDisableTiming)) != hipSuccess)
-      return hip_fail(e, "capture event");
+    if ((rc = ensure_branch(pl))) return rc;
     if (pl->graphs.size() >= (size_t)kGraphCache) {  // replace the least recently used
       size_t lru = 0;
       for (size_t q = 1; q < pl->graphs.size(); ++q)
@@ -1203,7 +1222,9 @@ struct bbfd_batch {
          off_len = 0, off_end = 0, ws_bytes = 0;
   int max_steps = 0;
   size_t max_tiles = 0;         // capacity of the tile table region
-  // launch shape (autotuned): rows per block, persistent blocks, z cells per tile
+  // launch shape (autotuned): rows per block, persistent blocks, z cells per
+  // tile; by = 0 runs every solve with its own step kernels instead (the
+  // per-solve shape, blocks = kchunk = 0)
   int by = 4, blocks = 1024, kchunk = 16;
   int max_mat = 1;              // largest material table (LDS staging size)
   std::vector<BatchTile> tiles;
@@ -1232,6 +1253,8 @@ namespace {
 void build_tiles(bbfd_batch *b) {
   b->tiles.clear();
   b->solve_end.clear();
+  b->live_solves.clear();
+  if (b->by == 0) return;  // the per-solve shape walks no table
   for (int s : b->order) {
     const bbfd_problem &p = b->plans[s]->prob;
     const int kc = std::max(1, std::min(b->kchunk, p.nz));
@@ -1350,9 +1373,27 @@ int mark_staging(bbfd_batch *b, hipStream_t s) {
   return e == hipSuccess ? BBFD_OK : hip_fail(e, "staging event record");
 }
 
+// The per-solve shape: each solve's prologue, steps (in two branches, as a
+// captured single solve) and epilogue, one solve after the other, in the order
+// of the problems.  Graph capture only, under the batch's lock.
+int enqueue_per_solve(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
+                      float *const *peak, char *ws, hipStream_t s) {
+  for (size_t q = 0; q < b->plans.size(); ++q) {
+    bbfd_plan *pl = b->plans[q];
+    std::lock_guard<std::mutex> lock(pl->mu);
+    int rc = ensure_branch(pl);
+    if (!rc)
+      rc = enqueue_solve(pl, mat[q], src[q], peak[q], ws + b->sub_off[q], s, nullptr,
+                         pl->branch ? pl->side_stream : nullptr);
+    if (rc) return rc;
+  }
+  return BBFD_OK;
+}
+
 int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
                   float *const *peak, char *ws, hipStream_t s, int steps = -1) {
   const size_t n = b->plans.size();
+  if (b->by == 0) return enqueue_per_solve(b, mat, src, peak, ws, s);
   // callers have waited for the staging (drop_graph precedes every capture and
   // every tuning pass)
   for (size_t q = 0; q < n; ++q)
@@ -1397,6 +1438,54 @@ int enqueue_batch(bbfd_batch *b, const uint8_t *const *mat, const float *const *
     if (rc) return rc;
   }
   return BBFD_OK;
+}
+
+// Autotuner probe of the per-solve shape: every solve's prologue, then one
+// captured graph of probe steps of every solve (its own step kernels, two
+// branches), launched once untimed and once between e0 and e1.
+int probe_per_solve(bbfd_batch *b, const uint8_t *const *mat, const float *const *src,
+                    float *const *peak, char *ws, hipStream_t s, int probe, hipEvent_t e0,
+                    hipEvent_t e1, float *ms) {
+  hipError_t e;
+  if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e, "capture stream");
+  const size_t n = b->plans.size();
+  for (size_t q = 0; q < n; ++q) {
+    bbfd_plan *pl = b->plans[q];
+    std::lock_guard<std::mutex> lock(pl->mu);
+    int rc = ensure_branch(pl);
+    if (!rc) rc = enqueue_prologue(pl, mat[q], peak[q], ws + b->sub_off[q], s);
+    if (rc) return rc;
+  }
+  if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+    return hip_fail(e, "begin capture");
+  int rc = BBFD_OK;
+  for (size_t q = 0; q < n && !rc; ++q) {
+    bbfd_plan *pl = b->plans[q];
+    std::lock_guard<std::mutex> lock(pl->mu);
+    rc = enqueue_steps(pl, mat[q], src[q], peak[q], ws + b->sub_off[q], b->cap_stream, 0,
+                       std::min(probe, pl->prob.n_steps), nullptr,
+                       pl->branch ? pl->side_stream : nullptr);
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : hip_fail(e, "end capture");
+  }
+  hipGraphExec_t x = nullptr;
+  if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "graph instantiate");
+  }
+  *ms = 0.f;
+  if ((e = hipGraphLaunch(x, s)) != hipSuccess || (e = hipEventRecord(e0, s)) != hipSuccess ||
+      (e = hipGraphLaunch(x, s)) != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess ||
+      (e = hipEventSynchronize(e1)) != hipSuccess || (e = hipEventElapsedTime(ms, e0, e1)) != hipSuccess)
+    rc = hip_fail(e, "per-solve probe");
+  (void)hipGraphExecDestroy(x);
+  (void)hipGraphDestroy(g);
+  return rc;
 }
 
 void drop_graph(bbfd_batch *b) {
@@ -1508,6 +1597,13 @@ uint64_t bbfd_batch_offset(const bbfd_batch *b, int32_t i) {
 
 int bbfd_batch_set_shape(bbfd_batch *b, int32_t by, int32_t blocks, int32_t kchunk) {
   if (!b) return fail(BBFD_EINVAL, "null batch");
+  if (by == 0) {  // per-solve shape
+    std::lock_guard<std::mutex> lock(b->mu);
+    b->by = b->blocks = b->kchunk = 0;
+    build_tiles(b);
+    drop_graph(b);
+    return BBFD_OK;
+  }
   if (!(by == 1 || by == 2 || by == 4 || by == 8) || blocks < 0 || kchunk < 1)
     return fail(BBFD_EINVAL, "bad launch shape (%d, %d, %d)", by, blocks, kchunk);
   size_t ntiles = 0;
@@ -1650,6 +1746,16 @@ int bbfd_batch_autotune(bbfd_batch *b, const uint8_t *const *mat, const float *c
           kc_ = kc;
         }
       }
+  {
+    std::lock_guard<std::mutex> lock(b->mu);
+    float ms = 0.f;
+    if ((rc = probe_per_solve(b, mat, src, peak, (char *)workspace, s, probe_steps, e0, e1, &ms)))
+      goto done;
+    if (ms < best) {
+      best = ms;
+      bb_ = bl_ = kc_ = 0;
+    }
+  }
   rc = bbfd_batch_set_shape(b, bb_, bl_, kc_);
   if (rc == BBFD_OK && best_ms) *best_ms = best;
   if (rc == BBFD_OK && cache_path && *cache_path) {

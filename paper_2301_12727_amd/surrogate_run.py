@@ -140,7 +140,7 @@ def val_loss(model, params, x, y, focus, batch=4):
 
 
 def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epochs=1000,
-          n_val=0, focus=0.0, val_every=5, flips=False):
+          n_val=0, focus=0.0, val_every=5, flips=False, init=None):
     """Adam on the (weighted) mean squared error of the log target,
     cosine-decayed learning rate over a time budget.  With n_val > 0 the last
     n_val samples are held out of training and the parameters with the lowest
@@ -151,6 +151,8 @@ def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epoc
     half-cell staggering of the grid).  Returns (params, loss history)."""
     import torch
     params = model.init_params(seed)
+    if init is not None:  # warm start from saved parameters
+        params.copy_(torch.as_tensor(init, dtype=torch.float32, device=params.device))
     st = model.train_state(params)
     rng = np.random.default_rng(seed)
     N = ds.x.shape[0] - n_val
@@ -328,6 +330,9 @@ def main():
                     help="1: mirror training batches in x / y at random")
     ap.add_argument("--val", type=int, default=200,
                     help="training samples held out to pick the best epoch (0: keep the last)")
+    ap.add_argument("--save", default=None,
+                    help="write the kept parameters here (float16 .npy, a warm start)")
+    ap.add_argument("--init", default=None, help="warm-start from a --save file")
     ap.add_argument("--focus", type=float, default=10.0,
                     help="loss weight 1 + focus * P/P_free (0: plain MSE of the log map)")
     args = ap.parse_args()
@@ -343,8 +348,11 @@ def main():
     ratio = float(np.mean(dtr.peak_post / dtr.free_post))
     model = sg.Surrogate(n=args.n, cin=4, width=args.width, layers=args.layers,
                          mx=args.modes, my=args.modes, mz=args.modes, loss_focus=args.focus)
+    init = np.load(args.init).astype(np.float32) if args.init else None
     params, hist = train(model, dtr, args.seconds, batch=args.batch, lr=args.lr,
-                         n_val=args.val, focus=args.focus, flips=bool(args.flips))
+                         n_val=args.val, focus=args.focus, flips=bool(args.flips), init=init)
+    if args.save:
+        np.save(args.save, params.cpu().numpy().astype(np.float16))
     res = evaluate(model, params, dev, ratio)
     if args.val > 0:
         scale = peak_calibration(model, params, dtr, args.val)
@@ -399,7 +407,8 @@ def main():
     out = {"config": {"n": args.n, "width": args.width, "layers": args.layers,
                       "modes": args.modes, "params": model.n_params, "train": args.train,
                       "loss_focus": args.focus, "val": args.val, "flips": args.flips,
-                      "eval": args.eval, "batch": args.batch, "seconds": args.seconds},
+                      "eval": args.eval, "batch": args.batch, "seconds": args.seconds,
+                      "init": args.init, "lr": args.lr},
            "generation_s": round(t_gen, 1), "training": hist, "eval": res,
            "train_mean_ratio": ratio, "gate_in_distribution_frac": in_dist,
            "gate_rejects_1MHz": not gate.accepts(odd_stats),

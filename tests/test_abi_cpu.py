@@ -140,6 +140,23 @@ def test_batch_rejects_empty_and_names_the_bad_problem():
     assert bb.lib().bbfd_last_error().decode().startswith("problem 2:")
 
 
+def test_batch_launch_shapes_host_side():
+    """bbfd_batch_set_shape (no device call): tiled shapes report their tile
+    count, by = 0 selects the per-solve shape (reported as all zeros), and an
+    unsupported row count is EINVAL."""
+    cases = [synth.random_small_case(40 + s, n=(24, 44), n_steps=30) for s in range(3)]
+    b = bb.Batch(cases)
+    b.set_shape(4, 0, 8)
+    n_tiles = sum(-(-c.nx // 64) * -(-c.ny // 4) * -(-c.nz // 8) for c in cases)
+    assert b.info()[1] == (4, 0, 8, n_tiles)
+    b.set_shape(0, 17, 5)
+    assert b.info()[1] == (0, 0, 0, 0)
+    with pytest.raises(bb.BBFDError) as e:
+        b.set_shape(3, 0, 8)
+    assert e.value.code == bb.EINVAL
+    b.close()
+
+
 def test_static_solve_rejects_plans_beyond_its_array():
     """bbfd_solve_static refuses a plan whose workspace exceeds its fixed
     per-GPU array before touching the device (no GPU needed)."""

@@ -59,7 +59,7 @@ def test_batched_equals_single_solves(tmp_path):
     b = bb.Batch(cases)
     ws = b.workspace()
     mats, srcs, peaks = batch_inputs(b, cases, ws)
-    for shape in ((4, 1024, 16), (1, 64, 4), (8, 3, 7), (2, 5000, 64), (4, 0, 8)):
+    for shape in ((4, 1024, 16), (1, 64, 4), (8, 3, 7), (2, 5000, 64), (4, 0, 8), (0, 0, 0)):
         say(f"[batch] shape {shape}")
         b.set_shape(*shape)
         b.solve(mats, srcs, peaks, ws)
