@@ -134,6 +134,49 @@ __device__ __forceinline__ float cpml_b(float *psi, uint32_t off, float q, float
 
 #define DPB(a, o, s4) dfw(ldb(a, (o) - (s4)), ldb(a, o), ldb(a, (o) + (s4)), ldb(a, (o) + 2 * (s4)))
 #define DMB(a, o, s4) dbw(ldb(a, (o) - 2 * (s4)), ldb(a, (o) - (s4)), ldb(a, o), ldb(a, (o) + (s4)))
+// The same with the centre value c = a at o already in a register.
+#define DPBC(a, o, s4, c) dfw(ldb(a, (o) - (s4)), c, ldb(a, (o) + (s4)), ldb(a, (o) + 2 * (s4)))
+#define DMBC(a, o, s4, c) dbw(ldb(a, (o) - 2 * (s4)), ldb(a, (o) - (s4)), c, ldb(a, (o) + (s4)))
+
+// x stencils without x-shifted loads.  In a wave whose 64 lanes are one whole
+// row segment inside the grid, the x neighbours of a cell are the
+// neighbouring lanes' values: whole-wave lane shifts (DPP wave_shr:1 /
+// wave_shl:1) move them, and only the two lanes at the segment's ends take a
+// cell of the neighbouring segment, a wave-uniform value read once per row
+// through the scalar cache.  The values and the arithmetic are those of the
+// loads they replace, so results are identical bit for bit.
+typedef __attribute__((address_space(4))) const float ScalarF32;
+// A float at a wave-uniform byte offset, through the scalar cache.
+__device__ __forceinline__ float ld_uniform(const float *base, uint32_t off) {
+  return *(const ScalarF32 *)(reinterpret_cast<const char *>(base) + off);
+}
+// Lane l receives lane l - 1's v (lane_up) or lane l + 1's (lane_down); the
+// lane with no such neighbour (0, resp. 63) receives edge.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ float lane_up(float v, float edge) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, v), 0x138,
+                                                               0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_down(float v, float edge) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, v), 0x130,
+                                                               0xf, 0xf, false));
+}
+// Byte offset of the row's first cell (lane 0's o; wave-uniform).
+__device__ __forceinline__ uint32_t row_start(uint32_t o) {
+  return __builtin_amdgcn_readfirstlane(o - 4u * threadIdx.x);
+}
+// DPB / DMB along x of field a, centre value c, row start ro.
+__device__ __forceinline__ float dpb_x(const float *a, uint32_t ro, float c) {
+  const float p1 = lane_down(c, ld_uniform(a, ro + 4 * kSeg));
+  return dfw(lane_up(c, ld_uniform(a, ro - 4)), c, p1,
+             lane_down(p1, ld_uniform(a, ro + 4 * kSeg + 4)));
+}
+__device__ __forceinline__ float dmb_x(const float *a, uint32_t ro, float c) {
+  const float m1 = lane_up(c, ld_uniform(a, ro - 4));
+  return dbw(lane_up(m1, ld_uniform(a, ro - 8)), m1, c, lane_down(c, ld_uniform(a, ro + 4 * kSeg)));
+}
 
 // Material index of the cell at element offset off of the padded index map
 // (uint8 entries, or uint16 for 12-bit CT maps).
@@ -147,7 +190,9 @@ __device__ __forceinline__ int ldi(const uint8_t *idx, uint32_t off) {
 // material table.  On plane ks the v_z faces also receive the source force
 // (src_c Re S - src_s Im S, scaled by the face buoyancy): a normal-traction
 // jump of 2 S across z = (ks + 1/2) dx.
-template <typename IdxT = uint8_t>
+// XD: the wave's row segment lies wholly inside the grid (x stencils by lane
+// shifts).
+template <typename IdxT = uint8_t, bool XD = false>
 __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lut, int bx, int j,
                                               int k0, int k1, float src_c, float src_s) {
   const Grid &g = A.g;
@@ -167,6 +212,7 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
   uint32_t c = (uint32_t)g.off(i, j, k0);
   for (int k = k0; k < k1; ++k, c += PL) {
     const uint32_t o = 4 * c;
+    const uint32_t ro = XD ? row_start(o) : 0u;
     const bool pz = in_layer(k, g.nz, g.L);
     const bool on_src = k == g.ks;
     const int cl = col.at(k, k0);
@@ -176,7 +222,9 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
     if (cl) {
       // acoustic path: the three normal stresses are equal and the shear
       // stresses vanish throughout the stencil's reach
-      float d1 = DPB(sxx, o, 4), e2 = DPB(sxx, o, P4), f3 = DPB(sxx, o, PL4);
+      const float s0 = ldb(sxx, o);
+      float d1 = XD ? dpb_x(sxx, ro, s0) : DPBC(sxx, o, 4, s0);
+      float e2 = DPBC(sxx, o, P4, s0), f3 = DPBC(sxx, o, PL4, s0);
       const float vxo = ldb_once(vx, o), vyo = ldb_once(vy, o), vzo = ldb_once(vz, o);
       const float q0 = px ? ldb_once(A.psi[0], o) : 0.f;
       const float q4 = py ? ldb_once(A.psi[4], o) : 0.f;
@@ -193,9 +241,13 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
     }
     const int m0 = ldi<IdxT>(idx, c), mx = ldi<IdxT>(idx, c + 1), my = ldi<IdxT>(idx, c + P),
               mz = ldi<IdxT>(idx, c + PL);
-    float d1 = DPB(sxx, o, 4), d2 = DMB(sxy, o, P4), d3 = DMB(sxz, o, PL4);
-    float e1 = DMB(sxy, o, 4), e2 = DPB(syy, o, P4), e3 = DMB(syz, o, PL4);
-    float f1 = DMB(sxz, o, 4), f2 = DMB(syz, o, P4), f3 = DPB(szz, o, PL4);
+    const float cxx = ldb(sxx, o), cxy = ldb(sxy, o), cxz = ldb(sxz, o);
+    float d1 = XD ? dpb_x(sxx, ro, cxx) : DPBC(sxx, o, 4, cxx);
+    float d2 = DMBC(sxy, o, P4, cxy), d3 = DMBC(sxz, o, PL4, cxz);
+    float e1 = XD ? dmb_x(sxy, ro, cxy) : DMBC(sxy, o, 4, cxy);
+    float e2 = DPB(syy, o, P4), e3 = DMB(syz, o, PL4);
+    float f1 = XD ? dmb_x(sxz, ro, cxz) : DMBC(sxz, o, 4, cxz);
+    float f2 = DMB(syz, o, P4), f3 = DPB(szz, o, PL4);
     const float vxo = ldb_once(vx, o), vyo = ldb_once(vy, o), vzo = ldb_once(vz, o);
     float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f, q4 = 0.f, q5 = 0.f, q6 = 0.f, q7 = 0.f, q8 = 0.f;
     if (px) { q0 = ldb_once(A.psi[0], o); q3 = ldb_once(A.psi[3], o); q6 = ldb_once(A.psi[6], o); }
@@ -399,7 +451,10 @@ struct AcCtx {
 };
 
 // One plane of the acoustic velocity update at byte offset o.  z0..z3: sxx at
-// planes k-1, k, k+1, k+2 of this column.
+// planes k-1, k, k+1, k+2 of this column.  XD: the wave's row segment lies
+// wholly inside the grid; the x neighbours come by lane shifts from z1 and
+// the segment-edge cells xm, xp, xp2 (of lanes 0, 63, 63) from the scalar cache.
+template <bool XD>
 struct VelAc {
   float xm, xp, xp2, ym, yp, yp2, vx, vy, vz, q0, q4, q8;
   float2 sq;
@@ -412,7 +467,13 @@ struct VelAc {
     cl = cls;
     pz = in_layer(k, A.g.nz, A.g.L);
     src = k == A.g.ks;
-    xm = ldb(sxx, o - 4); xp = ldb(sxx, o + 4); xp2 = ldb(sxx, o + 8);
+    if (XD) {
+      const uint32_t ro = row_start(o);
+      xm = ld_uniform(sxx, ro - 4); xp = ld_uniform(sxx, ro + 4 * kSeg);
+      xp2 = ld_uniform(sxx, ro + 4 * kSeg + 4);
+    } else {
+      xm = ldb(sxx, o - 4); xp = ldb(sxx, o + 4); xp2 = ldb(sxx, o + 8);
+    }
     ym = ldb(sxx, o - C.P4); yp = ldb(sxx, o + C.P4); yp2 = ldb(sxx, o + 2 * C.P4);
     vx = ldb_once(A.f[VX], o); vy = ldb_once(A.f[VY], o); vz = ldb_once(A.f[VZ], o);
     q0 = C.px ? ldb_once(A.psi[0], o) : 0.f;
@@ -425,6 +486,12 @@ struct VelAc {
   __device__ __forceinline__ void finish(const AcCtx &C, const float *lut, uint32_t o, float z0,
                                          float z1, float z2, float z3, float src_c, float src_s) {
     const StepArgs &A = *C.A;
+    if (XD) {
+      const float p1 = lane_down(z1, xp);
+      xp2 = lane_down(p1, xp2);
+      xm = lane_up(z1, xm);
+      xp = p1;
+    }
     float d1 = dfw(xm, z1, xp, xp2), e2 = dfw(ym, z1, yp, yp2), f3 = dfw(z0, z1, z2, z3);
     const float b = 1.f / lut[(cl - 1) * kLutW + kRhoS];
     if (C.px) d1 = cpml_b(A.psi[0], o, q0, C.tx.z, C.tx.w, d1);
@@ -454,6 +521,7 @@ __device__ __forceinline__ bool ac_setup(AcCtx &C, const StepArgs &A, int i, int
 // for them then does not include the completion of those stores (vector
 // memory operations retire in issue order), so each plane costs about one
 // memory latency instead of a load latency plus a store latency.
+template <bool XD = false>
 __device__ __forceinline__ void velocity_ac_tile(const StepArgs &A, const float *lut, int bx, int j,
                                                  int k0, int k1, float src_c, float src_s) {
   const int i = bx * kSeg + threadIdx.x;
@@ -465,11 +533,11 @@ __device__ __forceinline__ void velocity_ac_tile(const StepArgs &A, const float 
   uint32_t o = (uint32_t)A.g.off(i, j, k0) * 4u;
   float z0 = ldb(sxx, o - C.PL4), z1 = ldb(sxx, o), z2 = ldb(sxx, o + C.PL4),
         z3 = ldb(sxx, o + 2 * C.PL4);
-  VelAc cur;
+  VelAc<XD> cur;
   cur.load(C, o, k0, col.at(k0, k0), so);
   float h = (k0 + 1 < k1) ? ldb(sxx, o + 3 * C.PL4) : 0.f;  // plane k0 + 3, if used
   for (int k = k0; k < k1; ++k, o += C.PL4) {
-    VelAc nxt;
+    VelAc<XD> nxt;
     float hn = 0.f;
     if (k + 1 < k1) {
       nxt.load(C, o + C.PL4, k + 1, col.at(k + 1, k0), so);
@@ -565,7 +633,9 @@ __device__ __forceinline__ void stress_ac_tile(const StepArgs &A, const float *l
 // of the velocity kernels, operation for operation (with the CPML memory term
 // for faces in the x layer, see XFace), so the results equal the two-pass step
 // bit for bit.  It moves 32 bytes per cell update (sigma_xx and v read,
-// written) instead of 48.
+// written) instead of 48.  Away from the x layer the x stencils of sigma_xx
+// and v_x come by lane shifts (9 of the 22 loads of a plane), which the
+// memory pipeline, the kernel's first limit, no longer has to serve.
 __device__ __forceinline__ float vnew(float vold, float b, float m1, float p0, float p1, float p2) {
   return fmaf(b, dfw(m1, p0, p1, p2), vold);
 }
@@ -638,11 +708,26 @@ __device__ __forceinline__ void deep_tile(const StepArgs &A, const float *lut, i
   }
   for (int k = k0; k < k1; ++k, o += PL4, qo += QL4) {
     // x stencil of sxx on this row and plane, y stencil on this column
-    const float xm3 = ldb(sxx, o - 12), xm2 = ldb(sxx, o - 8), xm1 = ldb(sxx, o - 4);
-    const float xp1 = ldb(sxx, o + 4), xp2 = ldb(sxx, o + 8), xp3 = ldb(sxx, o + 12);
+    float xm3, xm2, xm1, xp1, xp2, xp3, ux2, ux1, ux0, uxp;
+    if (!XL) {  // every lane of the wave is inside the grid: lane shifts
+      const uint32_t ro = row_start(o);
+      xm1 = lane_up(s3, ld_uniform(sxx, ro - 4));
+      xm2 = lane_up(xm1, ld_uniform(sxx, ro - 8));
+      xm3 = lane_up(xm2, ld_uniform(sxx, ro - 12));
+      xp1 = lane_down(s3, ld_uniform(sxx, ro + 4 * kSeg));
+      xp2 = lane_down(xp1, ld_uniform(sxx, ro + 4 * kSeg + 4));
+      xp3 = lane_down(xp2, ld_uniform(sxx, ro + 4 * kSeg + 8));
+      ux0 = ldb(vx, o);
+      ux1 = lane_up(ux0, ld_uniform(vx, ro - 4));
+      ux2 = lane_up(ux1, ld_uniform(vx, ro - 8));
+      uxp = lane_down(ux0, ld_uniform(vx, ro + 4 * kSeg));
+    } else {
+      xm3 = ldb(sxx, o - 12); xm2 = ldb(sxx, o - 8); xm1 = ldb(sxx, o - 4);
+      xp1 = ldb(sxx, o + 4); xp2 = ldb(sxx, o + 8); xp3 = ldb(sxx, o + 12);
+      ux2 = ldb(vx, o - 8); ux1 = ldb(vx, o - 4); ux0 = ldb(vx, o); uxp = ldb(vx, o + 4);
+    }
     const float ym3 = ldb(sxx, o - 3 * P4), ym2 = ldb(sxx, o - 2 * P4), ym1 = ldb(sxx, o - P4);
     const float yp1 = ldb(sxx, o + P4), yp2 = ldb(sxx, o + 2 * P4), yp3 = ldb(sxx, o + 3 * P4);
-    const float ux2 = ldb(vx, o - 8), ux1 = ldb(vx, o - 4), ux0 = ldb(vx, o), uxp = ldb(vx, o + 4);
     const float uy2 = ldb(vy, o - 2 * P4), uy1 = ldb(vy, o - P4), uy0 = ldb(vy, o),
                 uyp = ldb(vy, o + P4);
     const bool more = k + 1 < k1;
@@ -724,8 +809,11 @@ __global__ void __launch_bounds__(kSeg * kRows)
   }
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  velocity_tile<IdxT>(A, lds ? s_lut : A.lut, bx, by * kRows + wave_row(), k0, k1, A.src_c,
-                      A.src_s);
+  const float *lut = lds ? s_lut : A.lut;
+  if ((bx + 1) * kSeg <= A.g.nx)  // whole segment inside the grid: lane shifts
+    velocity_tile<IdxT, true>(A, lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
+  else
+    velocity_tile<IdxT, false>(A, lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
 }
 
 template <typename IdxT>
@@ -755,7 +843,10 @@ __global__ void __launch_bounds__(kSeg * kRows)
   __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  velocity_ac_tile(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
+  if ((bx + 1) * kSeg <= A.g.nx)
+    velocity_ac_tile<true>(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
+  else
+    velocity_ac_tile<false>(A, s_lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
 }
 
 __global__ void __launch_bounds__(kSeg * kRows)

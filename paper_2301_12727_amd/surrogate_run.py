@@ -196,36 +196,52 @@ def train(model, ds: Dataset, seconds: float, batch=4, lr=1e-3, seed=0, max_epoc
     return best, hist
 
 
-def predict(model, params, x, batch=4):
+def predict(model, params, x, batch=4, tta=False):
+    """Log-map predictions for x.  With tta, the mean of the predictions for
+    the input and its mirror images in x, in y and in both (each mirrored
+    back): the training batches were mirrored the same way."""
     import torch
     out = torch.empty((x.shape[0], 1) + x.shape[2:], dtype=torch.float32, device=x.device)
+    if not tta:
+        for s in range(0, x.shape[0], batch):
+            model.forward(params, x[s:s + batch], out[s:s + batch])
+        return out
+    mirrors = ([4], [3], [3, 4])
     for s in range(0, x.shape[0], batch):
-        model.forward(params, x[s:s + batch], out[s:s + batch])
+        xb = x[s:s + batch]
+        acc = out[s:s + batch]
+        model.forward(params, xb, acc)
+        yb = torch.empty_like(acc)
+        for d in mirrors:
+            model.forward(params, torch.flip(xb, d).contiguous(), yb)
+            acc += torch.flip(yb, d)
+        acc /= 1 + len(mirrors)
     return out
 
 
-def predicted_peaks(model, params, ds: Dataset, idx) -> np.ndarray:
+def predicted_peaks(model, params, ds: Dataset, idx, tta=False) -> np.ndarray:
     """Post-skull peak of the network's map for samples idx of ds (masks kept)."""
     import torch
     sel = torch.as_tensor(np.asarray(idx), device=ds.x.device)
-    yhat = predict(model, params, ds.x.index_select(0, sel)).cpu().numpy()[:, 0]
+    yhat = predict(model, params, ds.x.index_select(0, sel), tta=tta).cpu().numpy()[:, 0]
     return np.array([np.where(ds.masks[q], ds.pref[q] * np.exp(yhat[r]), -1.0).max()
                      for r, q in enumerate(idx)])
 
 
-def peak_calibration(model, params, ds: Dataset, n_val: int) -> float:
+def peak_calibration(model, params, ds: Dataset, n_val: int, tta=False) -> float:
     """Median ratio of the FDTD post-skull peak to the network's on the n_val
     held-out training samples (the epoch-selection split): one scale that
     removes a systematic bias of the predicted focal pressure, fitted without
     the evaluation seeds."""
     idx = list(range(ds.x.shape[0] - n_val, ds.x.shape[0]))
-    return float(np.median(ds.peak_post[idx] / predicted_peaks(model, params, ds, idx)))
+    return float(np.median(ds.peak_post[idx] / predicted_peaks(model, params, ds, idx, tta)))
 
 
-def evaluate(model, params, ds: Dataset, train_ratio: float, scale: float = 1.0) -> dict:
+def evaluate(model, params, ds: Dataset, train_ratio: float, scale: float = 1.0,
+             tta=False) -> dict:
     """Focal errors of the surrogate (its peak times scale) and of the
     no-learning baseline on ds."""
-    yhat = predict(model, params, ds.x).cpu().numpy()[:, 0]
+    yhat = predict(model, params, ds.x, tta=tta).cpu().numpy()[:, 0]
     errs, dists, base = [], [], []
     for q in range(ds.x.shape[0]):
         mask = ds.masks[q]
@@ -333,13 +349,20 @@ def main():
     ap.add_argument("--save", default=None,
                     help="write the kept parameters here (float16 .npy, a warm start)")
     ap.add_argument("--init", default=None, help="warm-start from a --save file")
+    ap.add_argument("--train-start", type=int, default=10000,
+                    help="first training seed (evaluation seeds are 20000+, the 1 MHz case 30000)")
+    ap.add_argument("--tta", type=int, default=1,
+                    help="1: also evaluate with mirror averaging (input mirrored in x, y, both)")
     ap.add_argument("--focus", type=float, default=10.0,
                     help="loss weight 1 + focus * P/P_free (0: plain MSE of the log map)")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     synth = _synth()
-    tr_seeds = list(range(10000, 10000 + args.train))
+    tr_seeds = list(range(args.train_start, args.train_start + args.train))
+    held = set(range(20000, 20000 + args.eval)) | {30000}
+    if held & set(tr_seeds):
+        raise SystemExit("training seeds overlap the evaluation seeds or the 1 MHz case")
     ev_seeds = list(range(20000, 20000 + args.eval))
     t0 = time.time()
     dtr = generate(tr_seeds, args.n, keep_masks=args.val > 0)
@@ -358,6 +381,12 @@ def main():
         scale = peak_calibration(model, params, dtr, args.val)
         res["calibration_scale"] = scale
         res["calibrated"] = evaluate(model, params, dev, ratio, scale)
+    if args.tta:
+        res["tta"] = evaluate(model, params, dev, ratio, tta=True)
+        if args.val > 0:
+            scale = peak_calibration(model, params, dtr, args.val, tta=True)
+            res["tta"]["calibration_scale"] = scale
+            res["tta"]["calibrated"] = evaluate(model, params, dev, ratio, scale, tta=True)
     gate = Gate(dtr.stats)
     in_dist = float(np.mean([gate.accepts(s) for s in dev.stats]))
     odd = synth.surrogate_case(30000, args.n)
@@ -408,7 +437,7 @@ def main():
                       "modes": args.modes, "params": model.n_params, "train": args.train,
                       "loss_focus": args.focus, "val": args.val, "flips": args.flips,
                       "eval": args.eval, "batch": args.batch, "seconds": args.seconds,
-                      "init": args.init, "lr": args.lr},
+                      "init": args.init, "lr": args.lr, "train_start": args.train_start},
            "generation_s": round(t_gen, 1), "training": hist, "eval": res,
            "train_mean_ratio": ratio, "gate_in_distribution_frac": in_dist,
            "gate_rejects_1MHz": not gate.accepts(odd_stats),
