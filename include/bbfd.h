@@ -159,15 +159,20 @@ int bbfd_array_rayleigh(const bbfd_plan *plan, const bbfd_element *elements, int
    arrives at the target in phase.  w (host) receives 2 n doubles (re, im). */
 int bbfd_array_steer(const bbfd_plan *plan, const bbfd_element *elements, int32_t n,
                      const double *target, double *w);
-/* Refocusing through the map (time reversal).  (1) A solve of mat with a unit
-   force on the v_z face of the target cell (i, j, k) (k beyond the source
-   plane, inside the interior) in place of the transducer source, recording the
-   complex phasor of v_z on the faces of the source plane over the last period,
-   (2/N_T) sum v_z exp(-i omega t_n), t_n = (n + 1/2) dt; (2) the Rayleigh
+/* Refocusing through the map (time reversal).  (1) The point source at the
+   target cell (i, j, k) (k at least two planes beyond the source plane, inside
+   the interior), in place of the transducer source: unit z forces pushing
+   outward on the two v_z faces of the cell (+1 on face k, -1 on face k - 1),
+   which for the near-axial waves a focus collects acts as a monopole, so the
+   record is the transfer to the pressure at the target (a single z force
+   would give the transfer to v_z, whose sign flips for waves reflected back
+   from beyond the target); two solves, one per face, record the complex
+   phasor of v_z on the faces of the source plane over the last period,
+   (2/N_T) sum v_z exp(-i omega t_n), t_n = (n + 1/2) dt, summed; (2) the Rayleigh
    integral of that plane (normal velocity, cells of area dx^2 at
    z = (source_k + 1/2) dx) to every element centre, p_e; (3) the drives
    w_e = conj(p_e) / |p_e| (host, 2 n doubles).  field (host, may be NULL)
-   receives the p_e.  peak (dev) receives the point-source solve's peak map;
+   receives the p_e.  peak (dev) receives the second point-source solve's peak map;
    workspace as bbfd_solve.  Synchronises stream. */
 int bbfd_array_refocus(const bbfd_plan *plan, const uint8_t *mat, const bbfd_element *elements,
                        int32_t n, const int32_t *cell, float *peak, double *w, double *field,

@@ -18,10 +18,15 @@ Readings:
     and the array's field is the sum over elements (linearity);
   * steering in water: w_e = exp(+i k |c_e - T|) for element centre c_e and
     target T (the waves arrive in phase);
-  * the point source is a unit force on the v_z face of the target cell, the
-    solver's source mechanism applied to one cell; the interface record is the
-    phasor of v_z on the faces of the source plane over the last period,
-    (2 / N_T) sum_n v_z exp(-i omega t_n), t_n = (n + 1/2) dt;
+  * the point source is a pair of unit z forces pushing outward on the two
+    v_z faces of the target cell (+1 on the face above, -1 on the face below),
+    the solver's source mechanism applied to one cell: for the near-axial
+    waves a focus collects it acts as a monopole, so by reciprocity the record
+    is the transfer to the pressure at the target (one z force would give the
+    transfer to v_z, whose sign flips for waves reflected back from beyond the
+    target); the interface record is the phasor of v_z on the faces of the
+    source plane over the last period, (2 / N_T) sum_n v_z exp(-i omega t_n),
+    t_n = (n + 1/2) dt, of the pair's field (one solve per face, summed);
   * back-propagation: the first Rayleigh integral of that plane (normal
     velocity, cells of area dx^2) at the element centres;
   * refocused drives: w_e = conj(p_e) / |p_e| (phase conjugation, unit
@@ -76,16 +81,16 @@ def steer(rows, target, freq_hz):
     return np.exp(1j * k * r)
 
 
-def record(case, cell):
+def record_face(case, i, j, kf, force):
     """Phasor of v_z on the faces of the source plane over the last period of a
-    solve of case.mat driven by a unit z force on the target cell (i, j, k)."""
-    i, j, k = cell
+    solve of case.mat driven by a z force of the given value on the v_z face
+    above cell (i, j, kf)."""
     ks = case.pml if case.source_k < 0 else case.source_k
-    prob = problem_from_case(case, source_k=k)
+    prob = problem_from_case(case, source_k=kf)
     info, _ = setup(prob)
     nt, w, dt = info["steps_per_period"], info["omega"], info["dt"]
     src = np.zeros((case.ny, case.nx), dtype=np.complex128)
-    src[j, i] = 1.0
+    src[j, i] = force
     sim = Sim(prob, case.mat)
     acc = np.zeros((case.ny, case.nx), dtype=np.complex128)
     for n in range(case.n_steps):
@@ -94,6 +99,13 @@ def record(case, cell):
             acc += sim.field("vz")[ks] * np.exp(-1j * w * (n + 0.5) * dt)
     sim.close()
     return 2.0 * acc / nt
+
+
+def record(case, cell):
+    """The interface record of the point source at the target cell (i, j, k):
+    +1 on the v_z face above the cell, -1 on the face below it."""
+    i, j, k = cell
+    return record_face(case, i, j, k, 1.0) + record_face(case, i, j, k - 1, -1.0)
 
 
 def backprop(case, plane, centres):

@@ -29,6 +29,7 @@ hipError_t launch_tile_lists(const StepArgs &a, uint8_t *kind, int *const *lists
                              hipStream_t s);
 hipError_t launch_deep(const StepArgs &a, const int *const *lists, const int *counts,
                        hipStream_t s);
+hipError_t launch_lut_columns(float *lut, int n_mat, hipStream_t s);
 hipError_t launch_batch_kinds(const StepArgs *desc, BatchTile *tiles, int n_tiles, int by,
                               hipStream_t s);
 hipError_t launch_pack(const uint8_t *mat, uint8_t *idx, const Grid &g, int n_mat, int idx16,
@@ -316,7 +317,8 @@ void layout(bbfd_plan *pl) {
   pl->off_status = o; o += 256;
   const bool idx16 = p.index_bits == 16;
   pl->off_lut = o;
-  o += round_up((size_t)(idx16 ? kMaxMaterials16 : kMaxMaterials) * kLutW * sizeof(float), 256);
+  o += round_up((size_t)(idx16 ? kMaxMaterials16 * kLutW16 : kMaxMaterials * kLutW) * sizeof(float),
+                256);
   pl->off_pml = o; o += round_up(((size_t)p.nx + p.ny + p.nz) * sizeof(float4), 256);
   pl->off_pv = o; o += round_up(argmax_partials() * sizeof(float), 256);
   pl->off_pi = o; o += round_up(argmax_partials() * sizeof(long long), 256);
@@ -440,6 +442,9 @@ int enqueue_prologue(const bbfd_plan *pl, const uint8_t *mat, float *peak, char 
                           ((size_t)p.nx + p.ny + p.nz) * sizeof(float4), hipMemcpyHostToDevice,
                           s)) != hipSuccess)
     return hip_fail(e, "layer-table upload");
+  if (p.index_bits == 16 &&
+      (e = launch_lut_columns((float *)(ws + pl->off_lut), p.n_materials, s)) != hipSuccess)
+    return hip_fail(e, "table columns");
   if ((e = launch_fill((float *)(ws + pl->off_status), 256 / sizeof(float), 0.f, s)) != hipSuccess)
     return hip_fail(e, "status clear");
   if ((e = launch_fill((float *)(ws + pl->off_state),
@@ -498,7 +503,8 @@ constexpr int kStepKernels = 5;
 struct Record {
   int ks;
   int k_rec;
-  float2 *phasor;  // [ny][nx], cleared here
+  float2 *phasor;  // [ny][nx], cleared here unless accumulate
+  bool accumulate = false;
 };
 
 // Steps [n0, n1) of a solve whose prologue has been enqueued (arguments as
@@ -583,7 +589,7 @@ int enqueue_solve(const bbfd_plan *pl, const uint8_t *mat, const float *src, flo
   const bbfd_problem &p = pl->prob;
   int rc = enqueue_prologue(pl, mat, peak, ws, s, pinned);
   if (rc) return rc;
-  if (rec) {
+  if (rec && !rec->accumulate) {
     hipError_t e = launch_fill((float *)rec->phasor, 2LL * p.nx * p.ny, 0.f, s);
     if (e != hipSuccess) return hip_fail(e, "phasor clear");
   }
@@ -919,9 +925,10 @@ int bbfd_array_refocus(const bbfd_plan *cpl, const uint8_t *mat, const bbfd_elem
   bbfd_plan *pl = const_cast<bbfd_plan *>(cpl);
   const bbfd_problem &p = pl->prob;
   const int it = cell[0], jt = cell[1], kt = cell[2];
-  if (it < p.pml || it >= p.nx - p.pml || jt < p.pml || jt >= p.ny - p.pml || kt <= pl->ks ||
+  if (it < p.pml || it >= p.nx - p.pml || jt < p.pml || jt >= p.ny - p.pml || kt <= pl->ks + 1 ||
       kt >= p.nz - p.pml)
-    return fail(BBFD_EINVAL, "target cell (%d, %d, %d) must lie in the interior beyond the source plane",
+    return fail(BBFD_EINVAL,
+                "target cell (%d, %d, %d) must lie in the interior, two planes beyond the source plane",
                 it, jt, kt);
   {
     std::lock_guard<std::mutex> lock(pl->mu);
@@ -932,12 +939,22 @@ int bbfd_array_refocus(const bbfd_plan *cpl, const uint8_t *mat, const bbfd_elem
   float2 *point = (float2 *)(ws + pl->off_aux);
   float2 *ph = point + (size_t)p.nx * p.ny;
   hipError_t e;
-  // a unit z force on the v_z face of the target cell
+  // the point source: unit z forces pushing outward on the two v_z faces of
+  // the target cell, +1 on the face above it (plane kt) and -1 on the face
+  // below (plane kt - 1), recorded by two solves into one phasor (the record
+  // is linear in the source)
   if ((e = launch_fill((float *)point, 2LL * p.nx * p.ny, 0.f, s)) != hipSuccess ||
       (e = launch_fill((float *)(point + (size_t)jt * p.nx + it), 1, 1.f, s)) != hipSuccess)
     return hip_fail(e, "point source");
   Record rec{kt, pl->ks, ph};
   if ((rc = enqueue_solve(pl, mat, (const float *)point, peak, ws, s, nullptr, nullptr, true, &rec)))
+    return rc;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "record solve");
+  if ((rc = bbfd_status(pl, ws, nullptr, nullptr, stream))) return rc;
+  if ((e = launch_fill((float *)(point + (size_t)jt * p.nx + it), 1, -1.f, s)) != hipSuccess)
+    return hip_fail(e, "point source");
+  Record below{kt - 1, pl->ks, ph, true};
+  if ((rc = enqueue_solve(pl, mat, (const float *)point, peak, ws, s, nullptr, nullptr, true, &below)))
     return rc;
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "record solve");
   if ((rc = bbfd_status(pl, ws, nullptr, nullptr, stream))) return rc;

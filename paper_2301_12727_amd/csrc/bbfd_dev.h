@@ -44,6 +44,17 @@ enum LutField {
 };
 constexpr int kMaxMaterials = 256;      // rows of an 8-bit map's table (staged in LDS)
 constexpr int kMaxMaterials16 = 4096;   // rows of a 16-bit map's table (12-bit CT levels)
+// A 16-bit map's table region holds, after its kMaxMaterials16 rows, two
+// columns of it that the general kernels stage in LDS: the buoyancy input
+// kRhoS (one float per material) and the edge inputs kInvMu, kTauS (one
+// float2 per material).  kLutW + 3 floats per material in all.
+constexpr int kLutW16 = kLutW + 3;
+__host__ __device__ inline const float *rho_column(const float *lut) {
+  return lut + (size_t)kMaxMaterials16 * kLutW;
+}
+__host__ __device__ inline const float2 *edge_column(const float *lut) {
+  return reinterpret_cast<const float2 *>(lut + (size_t)kMaxMaterials16 * (kLutW + 1));
+}
 
 // Row segments: the kernels' waves cover 64 consecutive x cells of one row.
 // A segment's class is m + 1 when every cell within two cells of it (the

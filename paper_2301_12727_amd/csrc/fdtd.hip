@@ -80,6 +80,11 @@ __device__ __forceinline__ void stage_lut(float *s_lut, const float *lut, int n_
   const int nt = blockDim.x * blockDim.y, t0 = threadIdx.y * blockDim.x + threadIdx.x;
   for (int t = t0; t < n_mat * kLutW; t += nt) s_lut[t] = lut[t];
 }
+// Copies n floats into LDS (whole block; caller syncs).
+__device__ __forceinline__ void stage_floats(float *dst, const float *src, int n) {
+  const int nt = blockDim.x * blockDim.y, t0 = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int t = t0; t < n; t += nt) dst[t] = src[t];
+}
 
 // Wave-uniform class reader of one segment's z column: bytes are fetched as
 // 32-bit words through the scalar cache, the next word one group early.
@@ -192,9 +197,13 @@ __device__ __forceinline__ int ldi(const uint8_t *idx, uint32_t off) {
 // jump of 2 S across z = (ks + 1/2) dx.
 // XD: the wave's row segment lies wholly inside the grid (x stencils by lane
 // shifts).
+// lut: for 8-bit maps the material table (rows of kLutW); for 16-bit maps
+// the buoyancy column (one float per material), both in LDS.
 template <typename IdxT = uint8_t, bool XD = false>
 __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lut, int bx, int j,
                                               int k0, int k1, float src_c, float src_s) {
+  constexpr int RS = sizeof(IdxT) == 1 ? kLutW : 1;  // floats from one material's kRhoS to the next
+  const float *rho = sizeof(IdxT) == 1 ? lut + kRhoS : lut;
   const Grid &g = A.g;
   const int i = bx * kSeg + threadIdx.x;
   if (i >= g.nx || j >= g.ny) return;
@@ -229,7 +238,7 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
       const float q0 = px ? ldb_once(A.psi[0], o) : 0.f;
       const float q4 = py ? ldb_once(A.psi[4], o) : 0.f;
       const float q8 = pz ? ldb_once(A.psi[8], o) : 0.f;
-      const float b = 1.f / lut[(cl - 1) * kLutW + kRhoS];
+      const float b = 1.f / rho[(cl - 1) * RS];
       if (px) d1 = cpml_b(A.psi[0], o, q0, tx.z, tx.w, d1);
       if (py) e2 = cpml_b(A.psi[4], o, q4, ty.z, ty.w, e2);
       if (pz) f3 = cpml_b(A.psi[8], o, q8, tz.z, tz.w, f3);
@@ -253,10 +262,10 @@ __device__ __forceinline__ void velocity_tile(const StepArgs &A, const float *lu
     if (px) { q0 = ldb_once(A.psi[0], o); q3 = ldb_once(A.psi[3], o); q6 = ldb_once(A.psi[6], o); }
     if (py) { q1 = ldb_once(A.psi[1], o); q4 = ldb_once(A.psi[4], o); q7 = ldb_once(A.psi[7], o); }
     if (pz) { q2 = ldb_once(A.psi[2], o); q5 = ldb_once(A.psi[5], o); q8 = ldb_once(A.psi[8], o); }
-    const float r0 = lut[m0 * kLutW + kRhoS];
-    const float bx = 2.f / (r0 + lut[mx * kLutW + kRhoS]);
-    const float by = 2.f / (r0 + lut[my * kLutW + kRhoS]);
-    const float bz = 2.f / (r0 + lut[mz * kLutW + kRhoS]);
+    const float r0 = rho[m0 * RS];
+    const float bx = 2.f / (r0 + rho[mx * RS]);
+    const float by = 2.f / (r0 + rho[my * RS]);
+    const float bz = 2.f / (r0 + rho[mz * RS]);
     if (px) {
       d1 = cpml_b(A.psi[0], o, q0, tx.z, tx.w, d1);
       e1 = cpml_b(A.psi[3], o, q3, tx.x, tx.y, e1);
@@ -291,8 +300,10 @@ __device__ __forceinline__ float zener(float &s, float &r, float elastic, float 
   return s;
 }
 
-__device__ __forceinline__ float2 edge_in(const float *lut, int m) {
-  return *reinterpret_cast<const float2 *>(lut + m * kLutW + kInvMu);
+// Edge inputs {1/mu, tau_S} of material m: from the table's rows (es =
+// kLutW / 2 float2 per material, starting at kInvMu) or from a column (es = 1).
+__device__ __forceinline__ float2 edge_in(const float2 *edge, int es, int m) {
+  return edge[m * es];
 }
 
 // Shear component on an edge shared by cells with edge inputs a, b, c, d
@@ -306,10 +317,15 @@ __device__ __forceinline__ void edge(float &s, float &r, float e, float2 a, floa
 
 
 // Stress + memory update (Eq. 1 rows 4-9) and peak capture of one tile;
-// capture is this step's flag.
+// capture is this step's flag.  lut: the material table's rows (in LDS for
+// 8-bit maps); edge_col: for 16-bit maps, the edge-input column in LDS.
 template <typename IdxT = uint8_t>
 __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut, int bx, int j,
-                                            int k0, int k1, int capture) {
+                                            int k0, int k1, int capture,
+                                            const float2 *edge_col = nullptr) {
+  constexpr int ES = sizeof(IdxT) == 1 ? kLutW / 2 : 1;
+  const float2 *edge_tab =
+      sizeof(IdxT) == 1 ? reinterpret_cast<const float2 *>(lut + kInvMu) : edge_col;
   const Grid &g = A.g;
   const int i = bx * kSeg + threadIdx.x;
   if (i >= g.nx || j >= g.ny) return;
@@ -419,11 +435,11 @@ __device__ __forceinline__ void stress_tile(const StepArgs &A, const float *lut,
       lat = exx + eyy;
       zener(szz, rzz, fmaf(piu, th, -(muu2 * lat)), fmaf(pit, th, -(mut2 * lat)), ra, rb);
     }
-    const float2 e0 = edge_in(lut, m0), ex = edge_in(lut, mx);
-    const float2 ey = edge_in(lut, my), ez = edge_in(lut, mz);
-    edge(sxy, rxy, dyvx + dxvy, e0, ex, ey, edge_in(lut, mxy), ra, rb);
-    edge(sxz, rxz, dzvx + dxvz, e0, ex, ez, edge_in(lut, mxz), ra, rb);
-    edge(syz, ryz, dzvy + dyvz, e0, ey, ez, edge_in(lut, myz), ra, rb);
+    const float2 e0 = edge_in(edge_tab, ES, m0), ex = edge_in(edge_tab, ES, mx);
+    const float2 ey = edge_in(edge_tab, ES, my), ez = edge_in(edge_tab, ES, mz);
+    edge(sxy, rxy, dyvx + dxvy, e0, ex, ey, edge_in(edge_tab, ES, mxy), ra, rb);
+    edge(sxz, rxz, dzvx + dxvz, e0, ex, ez, edge_in(edge_tab, ES, mxz), ra, rb);
+    edge(syz, ryz, dzvy + dyvz, e0, ey, ez, edge_in(edge_tab, ES, myz), ra, rb);
     stb(sxxw, o, sxx); stb(syyw, o, syy); stb(szzw, o, szz);
     stb(rxxp, o, rxx); stb(ryyp, o, ryy); stb(rzzp, o, rzz);
     stb(sxyp, o, sxy); stb(sxzp, o, sxz); stb(syzp, o, syz);
@@ -795,21 +811,24 @@ extern __shared__ __align__(16) float s_lut[];
 // into three lists (acoustic / general / deep, each in tile order); block b
 // of a launch takes list entry xcd_band(b, count) and blocks beyond the
 // list's length exit at once.
-// General kernels: the material table of an 8-bit map is staged in LDS; the
-// up to 4096 rows of a 16-bit map's table are read through the caches.
+// General kernels: the material table of an 8-bit map is staged in LDS.  Of
+// the up to 4096 rows of a 16-bit map's table, the columns gathered for the
+// neighbours of a cell (buoyancy for the velocity update, edge inputs for the
+// shear update) are staged in LDS; the moduli, one float4 per cell, and the
+// fluid rows of the acoustic branches are read through the caches.
 template <typename IdxT>
 __global__ void __launch_bounds__(kSeg * kRows)
     k_velocity(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
-  const bool lds = sizeof(IdxT) == 1;
-  if (lds) {
-    stage_lut(s_lut, A.lut, A.n_mat);
-    __syncthreads();
-  }
+  if (sizeof(IdxT) == 1)
+    stage_lut(s_lut, A.lut, A.n_mat);  // the whole table
+  else
+    stage_floats(s_lut, rho_column(A.lut), A.n_mat);  // its buoyancy column
+  __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  const float *lut = lds ? s_lut : A.lut;
+  const float *lut = s_lut;
   if ((bx + 1) * kSeg <= A.g.nx)  // whole segment inside the grid: lane shifts
     velocity_tile<IdxT, true>(A, lut, bx, by * kRows + wave_row(), k0, k1, A.src_c, A.src_s);
   else
@@ -822,13 +841,15 @@ __global__ void __launch_bounds__(kSeg * kRows)
   const int n = *count;
   if ((int)blockIdx.x >= n) return;
   const bool lds = sizeof(IdxT) == 1;
-  if (lds) {
-    stage_lut(s_lut, A.lut, A.n_mat);
-    __syncthreads();
-  }
+  if (lds)
+    stage_lut(s_lut, A.lut, A.n_mat);  // the whole table
+  else  // its edge-input column (the moduli rows are read through the caches)
+    stage_floats(s_lut, reinterpret_cast<const float *>(edge_column(A.lut)), 2 * A.n_mat);
+  __syncthreads();
   int bx, by, k0, k1;
   tile_coords(A, list[xcd_band(blockIdx.x, n)], bx, by, k0, k1);
-  stress_tile<IdxT>(A, lds ? s_lut : A.lut, bx, by * kRows + wave_row(), k0, k1, A.capture);
+  stress_tile<IdxT>(A, lds ? s_lut : A.lut, bx, by * kRows + wave_row(), k0, k1, A.capture,
+                    reinterpret_cast<const float2 *>(s_lut));
 }
 
 // Rows the fluid-only kernels read: a lossless-fluid class m + 1 fits a byte,
@@ -1331,12 +1352,33 @@ __global__ void __launch_bounds__(kRedThreads)
 // ------------------------------------------------------------------ launchers
 
 static size_t lut_bytes(int n_mat) { return (size_t)n_mat * kLutW * sizeof(float); }
-// LDS of a launch: the whole table of an 8-bit map for the general kernels
-// (none for a 16-bit map: its table is read through the caches); the fluid
-// rows for the acoustic kernels and the fused step.
-static size_t lds_general(const StepArgs &a) { return a.idx16 ? 0 : lut_bytes(a.n_mat); }
+// LDS of a launch: for the general kernels the whole table of an 8-bit map,
+// or the column of a 16-bit map's table that the kernel gathers per neighbour
+// (buoyancy: up to 16 KB; edge inputs: up to 32 KB); the fluid rows for the
+// acoustic kernels and the fused step.
+static size_t lds_velocity(const StepArgs &a) {
+  return a.idx16 ? (size_t)a.n_mat * sizeof(float) : lut_bytes(a.n_mat);
+}
+static size_t lds_stress(const StepArgs &a) {
+  return a.idx16 ? (size_t)a.n_mat * sizeof(float2) : lut_bytes(a.n_mat);
+}
 static size_t lds_fluid(const StepArgs &a) {
   return lut_bytes(a.n_mat < kMaxMaterials ? a.n_mat : kMaxMaterials);
+}
+
+// The buoyancy and edge-input columns of a 16-bit map's table (rows [0,
+// n_mat)), written after its rows; see rho_column / edge_column.
+__global__ void k_lut_columns(float *lut, int n_mat) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mat) return;
+  const float *row = lut + (size_t)m * kLutW;
+  const_cast<float *>(rho_column(lut))[m] = row[kRhoS];
+  const_cast<float2 *>(edge_column(lut))[m] = make_float2(row[kInvMu], row[kTauS]);
+}
+
+hipError_t launch_lut_columns(float *lut, int n_mat, hipStream_t s) {
+  hipLaunchKernelGGL(k_lut_columns, dim3((n_mat + 255) / 256), dim3(256), 0, s, lut, n_mat);
+  return hipGetLastError();
 }
 
 // lists: [0] acoustic tile ids, [1] general tile ids (n_tiles ints each);
@@ -1347,10 +1389,10 @@ hipError_t launch_velocity(const StepArgs &a, const int *const *lists, const int
     hipLaunchKernelGGL(k_velocity_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_fluid(a), s, a,
                        lists[0], counts);
   else if (a.idx16)
-    hipLaunchKernelGGL(k_velocity<uint16_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a),
+    hipLaunchKernelGGL(k_velocity<uint16_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_velocity(a),
                        s, a, lists[1], counts + 1);
   else
-    hipLaunchKernelGGL(k_velocity<uint8_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a),
+    hipLaunchKernelGGL(k_velocity<uint8_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_velocity(a),
                        s, a, lists[1], counts + 1);
   return hipGetLastError();
 }
@@ -1369,10 +1411,10 @@ hipError_t launch_stress(const StepArgs &a, const int *const *lists, const int *
     hipLaunchKernelGGL(k_stress_ac, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_fluid(a), s, a,
                        lists[0], counts);
   else if (a.idx16)
-    hipLaunchKernelGGL(k_stress<uint16_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a), s,
+    hipLaunchKernelGGL(k_stress<uint16_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_stress(a), s,
                        a, lists[1], counts + 1);
   else
-    hipLaunchKernelGGL(k_stress<uint8_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_general(a), s,
+    hipLaunchKernelGGL(k_stress<uint8_t>, dim3(a.n_tiles), dim3(kSeg, kRows, 1), lds_stress(a), s,
                        a, lists[1], counts + 1);
   return hipGetLastError();
 }

@@ -281,6 +281,92 @@ def cap_array(focus, focal: float, aperture_radius: float, n: int, piston_radius
     return rows
 
 
+def flat_array(centre, aperture_radius: float, n: int, piston_radius: float,
+               rings: int) -> np.ndarray:
+    """n flat circular pistons on the plane z = centre[2], facing +z, on
+    ``rings`` annuli of equal area around ``centre`` (n // rings pistons each,
+    equally spaced in azimuth); rows as ``cap_array``, unit drive."""
+    c = np.asarray(centre, dtype=np.float64)
+    per = max(1, n // rings)
+    rows = []
+    for r in range(rings):
+        rho = aperture_radius * math.sqrt((r + 0.5) / rings)   # mid-area radius of the annulus
+        for q in range(per):
+            ph = 2 * math.pi * (q + 0.5 * (r % 2)) / per
+            rows.append((piston_radius, c[0] + rho * math.cos(ph), c[1] + rho * math.sin(ph), c[2],
+                         0.0, 0.0, 1.0, 1.0, 0.0))
+    return np.array(rows, dtype=np.float64)
+
+
+# The paper's multi-element transducers (Section 2), by what it states of
+# them: the number of elements or rings, the focal length F and F-number
+# (aperture diameter F / F#) of the curved ones, the diameter of the flat one,
+# and the frequencies it drives them at.  What it does not state -- element
+# size and layout -- is this module's choice: pistons covering half of the
+# radiating surface, a golden-angle spiral for the 128-element cap, and each
+# ring of an annular device as pistons sharing its radius (which steering on
+# the axis drives alike).
+DEVICES = {
+    # name: (pistons, rings (0: independent elements), F in m (None: flat),
+    #        aperture diameter in m, frequencies in Hz)
+    "H317": (128, 0, 135e-3, 135e-3 / 0.9, (250e3, 700e3)),
+    "CTX-500": (64, 4, 63.2e-3, 63.2e-3 / 0.98, (500e3,)),
+    "H246": (24, 2, None, 33.6e-3, (500e3,)),
+}
+
+
+def device_array(name: str, apex) -> np.ndarray:
+    """Element rows of one of the paper's devices with the centre of its
+    radiating face (the bowl's apex) at ``apex``, axis +z: the geometric focus
+    of a curved device is apex + (0, 0, F)."""
+    n, rings, F, D, _ = DEVICES[name]
+    a = np.asarray(apex, dtype=np.float64)
+    R = 0.5 * D
+    # piston centres within R - rp, so that every piston lies inside the aperture
+    if F is None:
+        area = math.pi * R * R
+        rp = math.sqrt(0.5 * area / (n * math.pi))
+        return flat_array(a, R - rp, n, rp, rings)
+    area = 2 * math.pi * F * F * (1.0 - math.sqrt(1.0 - (R / F) ** 2))
+    rp = math.sqrt(0.5 * area / (n * math.pi))
+    return cap_array(a + np.array([0.0, 0.0, F]), F, R - rp, n, rp, rings)
+
+
+def device_case(name: str, freq_hz: float, ppw: float = 6.0, seed: int = 1, skull: bool = True,
+                lateral: float | None = None, depth: float | None = None,
+                n_steps: int | None = None):
+    """A head-scale domain for one of the paper's devices: lateral extent
+    ``lateral`` (default: the aperture plus 10 mm), depth ``depth`` (default:
+    F + 30 mm for a curved device, 80 mm for the flat one), the device on the
+    middle column with its highest piston edge 3 mm before the source plane,
+    and (skull) the skull
+    shell of ``skull_case`` (outer radius 70 mm, outer surface 10 mm after the
+    source plane on the axis).  The step count (default) covers 1.5 passes
+    over the depth plus 4 periods.  Returns (case, element rows, geometric
+    focus cell (i, j, k); the cell 60 mm deep on the axis for the flat
+    device)."""
+    n_el, rings, F, D, _ = DEVICES[name]
+    dx = C_WATER / (freq_hz * ppw)
+    lat = lateral if lateral is not None else D + 10e-3
+    dep = depth if depth is not None else ((F + 30e-3) if F is not None else 80e-3)
+    pml = 8
+    nx = ny = int(math.ceil(lat / dx)) + 2 * pml
+    nz = int(math.ceil(dep / dx)) + 2 * pml
+    mats = skull_materials(freq_hz)
+    zs = (pml + 0.5) * dx
+    mat = (skull_map(nx, ny, nz, dx, zs, seed, r_out=70e-3, centre_depth=80e-3) if skull
+           else np.zeros((nz, ny, nx), dtype=np.uint8))
+    periods = math.ceil(1.5 * nz / ppw) + 4
+    steps = n_steps if n_steps is not None else periods * math.ceil(3.9 * ppw)
+    c = Case(f"{name}_{int(freq_hz / 1e3)}kHz", nx, ny, nz, pml, freq_hz, ppw, steps, mats, mat,
+             None)
+    rows = device_array(name, ((nx // 2) * dx, (ny // 2) * dx, 0.0))
+    apex_z = zs - 3e-3 - float(np.max(rows[:, 3] + rows[:, 0]))
+    rows[:, 3] += apex_z
+    fz = apex_z + (F if F is not None else 60e-3)
+    return c, rows, (nx // 2, ny // 2, int(round(fz / dx)))
+
+
 def array_for_case(case: "Case", elements: int = 32, rings: int = 0):
     """A phased array for a case in place of its bowl: a cap of aperture 0.6 x
     the smaller lateral extent, F#1, rim 3 mm (plus 0.2 wavelengths) before the

@@ -231,3 +231,38 @@ def test_16_bit_maps_allow_4096_rows_only_in_single_solves():
     with pytest.raises(bb.BBFDError) as e:
         bb.Batch([case])
     assert e.value.code == bb.EINVAL
+
+
+def test_device_presets_match_the_papers_stated_geometry():
+    """The paper's three devices (Section 2) as synthetic inputs: element or
+    ring counts, focal length and F-number (curved) or diameter (flat), and
+    the library's host steering of them: on the axis the pistons of one ring
+    get one drive, and steering the 128-element cap to its own geometric
+    focus drives every element alike."""
+    for name, (n, rings, F, D, freqs) in synth.DEVICES.items():
+        rows = synth.device_array(name, (0.0, 0.0, 0.0))
+        assert rows.shape == (n, 9)
+        lateral = np.hypot(rows[:, 1], rows[:, 2])
+        assert lateral.max() + rows[0, 0] <= 0.5 * D + 1e-12
+        if F is None:
+            assert np.all(rows[:, 3] == 0.0) and np.all(rows[:, 6] == 1.0)
+        else:
+            focus = np.array([0.0, 0.0, F])
+            dist = np.linalg.norm(rows[:, 1:4] - focus, axis=1)
+            assert np.allclose(dist, F, rtol=0, atol=1e-12)
+            axis = (focus - rows[:, 1:4]) / dist[:, None]
+            assert np.allclose(rows[:, 4:7], axis, atol=1e-12)
+            assert F / (2 * (lateral.max() + rows[0, 0])) >= F / D - 1e-12
+        if rings:
+            radii = np.unique(np.round(lateral, 9))
+            assert len(radii) == rings
+        plan = bb.Plan(32, 32, 32, freqs[0], 6.0, 10, synth.table1(freqs[0])["water"])
+        depth = (F if F is not None else 60e-3)
+        w = plan.array_steer(rows, (0.0, 0.0, depth + 5e-3))
+        ring_of = np.round(lateral, 9)
+        for r in np.unique(ring_of):
+            same = w[ring_of == r]
+            assert np.allclose(same, same[0], rtol=0, atol=1e-9) or rings == 0
+        if name == "H317":
+            w0 = plan.array_steer(rows, (0.0, 0.0, F))
+            assert np.allclose(w0, w0[0], rtol=0, atol=1e-9)
