@@ -132,6 +132,7 @@ struct bbfd_plan {
          off_energy = 0, off_aux = 0,
          ws_bytes = 0;
   int n_tiles = 0;
+  int n_fluid = 1;      // table rows the fluid-only kernels stage (see build_tables)
   bool deep = false;    // some tile can be deep: the fused step is launched
   bool branch = false;  // the captured steps run as two branches
   std::mutex mu;
@@ -263,6 +264,13 @@ int build_tables(bbfd_plan *pl) {
     o[kInvMu] = c[5] > 0 ? (float)(1.0 / (c[5] * s)) : INFINITY;
     o[kLossless] = (c[5] == 0.0 && c[2] == 0.0) ? 1.0f : 0.0f;  // no shear, no P memory
   }
+  // Only lossless fluids of index below 255 get a segment class, and the
+  // acoustic kernels and the fused step read the table rows of those classes
+  // alone: they stage the rows up to the last such fluid (a 12-bit CT table
+  // holds its fluid in row 0 and bone in the 4095 rows after it).
+  pl->n_fluid = 1;
+  for (int m = 0; m < std::min(p.n_materials, kMaxMaterials - 1); ++m)
+    if (pl->lut[(size_t)m * kLutW + kLossless] != 0.0f) pl->n_fluid = m + 1;
   const int dims[3] = {p.nx, p.ny, p.nz};
   float4 *t = pl->pmltab.data();
   for (int ax = 0; ax < 3; ++ax)
@@ -383,6 +391,7 @@ StepArgs step_args(const bbfd_plan *pl, const uint8_t *, const float *src, float
   a.keep = (const uint8_t *)(ws + pl->off_keep);
   a.lut = (const float *)(ws + pl->off_lut);
   a.n_mat = pl->prob.n_materials;
+  a.n_fluid = pl->n_fluid;
   const float4 *t = (const float4 *)(ws + pl->off_pml);
   a.pml.x = t;
   a.pml.y = t + pl->prob.nx;

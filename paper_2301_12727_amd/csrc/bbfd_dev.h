@@ -92,6 +92,7 @@ struct StepArgs {
                           // sigma_zz of this segment (within 2 rows / 2 planes)
   const float *lut;       // kLutW floats per material
   int n_mat;              // materials in lut
+  int n_fluid;            // rows [0, n_fluid) hold every fluid that has a segment class
   PmlTab pml;
   float *f[kNState];      // padded state arrays (read; shear stresses and memories
                           // are also written in place)

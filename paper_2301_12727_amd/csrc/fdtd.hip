@@ -852,9 +852,9 @@ __global__ void __launch_bounds__(kSeg * kRows)
                     reinterpret_cast<const float2 *>(s_lut));
 }
 
-// Rows the fluid-only kernels read: a lossless-fluid class m + 1 fits a byte,
-// so m < 255 and the first 256 rows suffice.
-__device__ __forceinline__ int fluid_rows(const StepArgs &A) { return min(A.n_mat, kMaxMaterials); }
+// Rows the fluid-only kernels read: those of the lossless fluids that have a
+// segment class (class m + 1 fits a byte, so m < 255), up to the last one.
+__device__ __forceinline__ int fluid_rows(const StepArgs &A) { return A.n_fluid; }
 
 __global__ void __launch_bounds__(kSeg * kRows)
     k_velocity_ac(StepArgs A, const int *__restrict__ list, const int *__restrict__ count) {
@@ -1362,9 +1362,7 @@ static size_t lds_velocity(const StepArgs &a) {
 static size_t lds_stress(const StepArgs &a) {
   return a.idx16 ? (size_t)a.n_mat * sizeof(float2) : lut_bytes(a.n_mat);
 }
-static size_t lds_fluid(const StepArgs &a) {
-  return lut_bytes(a.n_mat < kMaxMaterials ? a.n_mat : kMaxMaterials);
-}
+static size_t lds_fluid(const StepArgs &a) { return lut_bytes(a.n_fluid); }
 
 // The buoyancy and edge-input columns of a 16-bit map's table (rows [0,
 // n_mat)), written after its rows; see rho_column / edge_column.
