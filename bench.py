@@ -33,6 +33,7 @@ WORKLOADS = {
     "skull400": lambda: __import__("synth").skull400(),
     "skull200": lambda: __import__("synth").skull200(),
     "plate64": lambda: __import__("synth").plate_case(),
+    "skull200_ct12": lambda: __import__("synth").ct_case(__import__("synth").skull200(), 1),
 }
 
 
@@ -430,10 +431,12 @@ def paper_domain_section(bb, torch, repeats: int = 3) -> dict:
 
 def ct12_section(bb, torch, repeats: int = 3) -> dict:
     """The 200x200x280 skull at 500 kHz as a 12-bit CT map (uint16 indices into
-    4096 rows, the general kernels reading the table through the caches)
-    against the same grid with the 10-row 8-bit table: Gcell-updates/s of each
-    (median of ``repeats`` captured solves), and a q_c sweep (0.4, 1, 2, 3, 4)
-    of the 8-bit map as one batch against the same five solves one by one."""
+    4096 rows; the general kernels stage the table's buoyancy and edge-input
+    columns in LDS) against the same grid with the 10-row 8-bit table:
+    Gcell-updates/s of each (median of ``repeats`` captured solves), the
+    per-kernel time per step and the tile counts, and a q_c sweep (0.4, 1, 2,
+    3, 4) of the 8-bit map as one batch against the same five solves one by
+    one."""
     import numpy as np
     import synth
     dev = torch.device("cuda:0")
@@ -456,9 +459,13 @@ def ct12_section(bb, torch, repeats: int = 3) -> dict:
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         t = float(np.median(ts))
+        kms = plan.solve_profiled(mat, src, peak, ws)
         out[name] = {"gcell_updates_per_s": round(case.cells * case.n_steps / t / 1e9, 2),
                      "levels_in_map": int(len(np.unique(case.mat))),
-                     "table_rows": int(case.materials.shape[0])}
+                     "table_rows": int(case.materials.shape[0]),
+                     "kernel_ms_per_step": {f"k_{k}": round(m / case.n_steps, 4)
+                                            for k, m in zip(KERNELS, kms)},
+                     "tiles_acoustic_general_deep": list(plan.tile_counts(ws))}
         del ws, peak
         torch.cuda.empty_cache()
     qcs = (0.4, 1.0, 2.0, 3.0, 4.0)
@@ -562,7 +569,7 @@ def thermal_section(bb, torch, repeats: int = 3) -> dict:
     plan.source_rayleigh(case.transducer, src, ws)
     mat = torch.from_numpy(case.mat).to(dev)
     peak = torch.empty(plan.shape, dtype=torch.float32, device=dev)
-    plan.solve(mat, src, peak, ws)
+    plan.solve(mat, src, peak, ws, graph=False)  # direct launches: the BHTE loop is timed
     plan.status(ws)
     del ws
     ac, th = synth.thermal_materials(case.freq_hz)
@@ -605,6 +612,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-sweep section")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated sections to run alone (batched, energy_loss, thermal, "
+                         "ct12, paper_domain, phased_array), printing their JSON (for profiling)")
     ap.add_argument("--time-steps", type=int, default=None,
                     help="override the workload's time-step count (short profiling runs)")
     ap.add_argument("--capture-start", type=int, default=None,
@@ -621,6 +631,17 @@ def main():
 
     import torch
     import paper_2301_12727_amd as bb
+
+    if args.only:
+        sections = {"batched": batched_section, "energy_loss": energy_loss_section,
+                    "thermal": thermal_section, "ct12": ct12_section,
+                    "paper_domain": paper_domain_section, "phased_array": array_section}
+        res = {}
+        for name in args.only.split(","):
+            res[name] = sections[name](bb, torch)
+            torch.cuda.empty_cache()
+        print(json.dumps(res))
+        return
 
     if args.calibrate_copy:
         n = 1 << 28                       # 2^28 floats = 1 GiB read + 1 GiB written
