@@ -348,7 +348,9 @@ def _ptr_array(tensors):
 
 
 class Batch:
-    """Uneven sweep of independent solves run by one persistent captured graph."""
+    """Uneven sweep of independent solves run by one captured graph: tiled
+    kernels walking per-kind (solve, tile) tables, or every solve's own step
+    kernels one after the other (the per-solve shape); autotuned."""
 
     def __init__(self, cases, n_steps=None):
         self._plans_py = [Plan.from_case(c, n_steps=n_steps) for c in cases]  # validation, info
@@ -409,6 +411,8 @@ class Batch:
                                           sub.numel(), C.c_void_p(_stream(stream))))
 
     def set_shape(self, by, blocks, kchunk):
+        """Tiled launch shape (rows per block 1/2/4/8, persistent blocks or 0,
+        z cells per tile), or by = 0 for the per-solve shape."""
         _check(lib().bbfd_batch_set_shape(self.h, by, blocks, kchunk))
 
     def solve(self, mats, srcs, peaks, ws, stream=None):
