@@ -282,12 +282,14 @@ class Predictor:
     """Surrogate with the FDTD solve as fallback: a case the gate accepts (and
     whose grid is the network's n^3) is answered by the network (free field by
     the Rayleigh integral over the grid, features, forward pass, peak map =
-    free-field peak x exp(prediction)); any other case is solved by FDTD
-    (bbfd_solve).  Calls return (peak map [nz, ny, nx] on the device, "surrogate"
-    or "fdtd")."""
+    free-field peak x exp(prediction), times the peak calibration ``scale``
+    fitted on the validation split, see peak_calibration); any other case is
+    solved by FDTD (bbfd_solve).  Calls return (peak map [nz, ny, nx] on the
+    device, "surrogate" or "fdtd")."""
 
-    def __init__(self, model, params, gate: Gate, device="cuda"):
+    def __init__(self, model, params, gate: Gate, device="cuda", scale: float = 1.0):
         self.model, self.params, self.gate, self.device = model, params, gate, device
+        self.scale = float(scale)
         self.n = model.n
         self.counts = {"surrogate": 0, "fdtd": 0}
 
@@ -319,7 +321,7 @@ class Predictor:
             y = self.model.forward(self.params, x)
             L = case.pml
             pref = free.abs()[L:n - L, L:n - L, L:n - L].max()
-            peak = pref * torch.exp(y[0, 0])
+            peak = (self.scale * pref) * torch.exp(y[0, 0])
         else:
             src = torch.empty((case.ny, case.nx), dtype=torch.complex64, device=self.device)
             plan.source_rayleigh(case.transducer, src, ws)
