@@ -167,3 +167,46 @@ def test_back_to_back_batches_keep_their_own_pointers():
             idx, val = b.status(ws, i)
             assert_same_map(peaks[i].cpu().numpy(), single[i][0], idx, val, single[i][1],
                             single[i][2], (tag, i))
+
+
+def _deep_case(blob_x, src_k=-1):
+    """A 128 x 64 x 70 water grid with a solid blob: over 2048 tiles, so its
+    single solve runs the fused step of deep tiles in two captured branches."""
+    nx, ny, nz, pml, f = 128, 64, 70, 4, 500e3
+    mats = synth._rows(synth.table1(f)["water"], (1850.0, 2700.0, 1300.0, 80.0, 200.0))
+    mat = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mat[20:26, 8:18, blob_x[0]:blob_x[1]] = 1
+    case = synth.Case("deep", nx, ny, nz, pml, f, 6.0, 70, mats, mat, None)
+    case.source_k = src_k
+    dx, zs = case.dx, case.source_plane_z()
+    radius = 0.3 * min(nx, ny) * dx
+    focal = 2.4 * radius
+    fz = synth.bowl_focus_for_standoff(zs, radius, focal, (0.0, 0.0, 1.0), 2e-3)
+    case.transducer = synth.Transducer(1, radius, focal, (nx // 2 * dx, ny // 2 * dx, fz - focal),
+                                       (0.0, 0.0, 1.0))
+    return case
+
+
+def test_per_solve_shape_equals_single_solves_with_fused_steps():
+    """The per-solve batch shape on solves large enough for the fused step of
+    deep tiles and the two-branch capture (and one with the source plane moved
+    inside): each solve's own step kernels in the batch graph give the single
+    solves' maps bit for bit, over graph replays; the tiled shape (no fused
+    step) gives them too."""
+    cases = [_deep_case((70, 90)), _deep_case((20, 40), src_k=16), _deep_case((40, 60))]
+    single = []
+    for c in cases:
+        P, idx, val, plan = bb.run_case(c)
+        single.append((P.cpu().numpy(), idx, val))
+    b = bb.Batch(cases)
+    ws = b.workspace()
+    mats, srcs, peaks = batch_inputs(b, cases, ws)
+    for shape in ((0, 0, 0), (4, 0, 8)):
+        b.set_shape(*shape)
+        assert b.info()[1][0] == shape[0]
+        for _ in range(3):                    # capture, then replays
+            b.solve(mats, srcs, peaks, ws)
+        for i in range(len(cases)):
+            idx, val = b.status(ws, i)
+            assert_same_map(peaks[i].cpu().numpy(), single[i][0], idx, val, single[i][1],
+                            single[i][2], (shape, i))
