@@ -266,3 +266,18 @@ def test_device_presets_match_the_papers_stated_geometry():
         if name == "H317":
             w0 = plan.array_steer(rows, (0.0, 0.0, F))
             assert np.allclose(w0, w0[0], rtol=0, atol=1e-9)
+
+
+def test_device_cases_place_the_array_before_the_source_plane():
+    """synth.device_case: every piston edge lies 3 mm or more before the
+    source plane (the Rayleigh integral assumes the elements radiate into the
+    half-space of the grid), the target cell lies inside the interior, and the
+    step count covers 1.5 passes over the depth."""
+    for name, f in (("H317", 250e3), ("CTX-500", 500e3), ("H246", 500e3)):
+        case, rows, cell = synth.device_case(name, f, skull=False)
+        zs = (case.pml + 0.5) * case.dx
+        assert np.max(rows[:, 3] + rows[:, 0]) <= zs - 3e-3 + 1e-12
+        i, j, k = cell
+        L = case.pml
+        assert L <= i < case.nx - L and L <= j < case.ny - L and L + 2 <= k < case.nz - L
+        assert case.n_steps * 1.0 >= 1.5 * case.nz / case.ppw * 3.9 * case.ppw
