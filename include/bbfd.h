@@ -57,8 +57,10 @@ typedef struct {
    index_bits: 8 (or 0): the material map is uint8 and the table has up to 256
              rows; 16: the map is uint16 and the table has up to 4096 rows (CT
              values quantised at 12 bits, Section 2.2.2).  With 16-bit maps the
-             general kernels read the table through the caches instead of LDS,
-             and only fluids of index below 255 take the acoustic kernels. */
+             general kernels stage only the table's buoyancy and edge-input
+             columns in LDS (the workspace holds them after the rows) and read
+             each cell's moduli through the caches, and only fluids of index
+             below 255 take the acoustic kernels. */
 typedef struct {
   int32_t nx, ny, nz, pml;
   double freq_hz, ppw, qc, cfl_safety;
