@@ -12,7 +12,9 @@
 //   k_step_deep               : both half-steps of a deep tile in one pass
 // All are HBM-bandwidth-bound stencils.  x is the fastest (coalesced) axis
 // and each wave owns one 64-cell row segment, so the segment class (acoustic
-// or elastic branch) is wave-uniform.  Per block the material table is
+// or elastic branch) is wave-uniform, and in the fused step and the velocity
+// kernels the x neighbours of a whole segment come by lane shifts.  Per block
+// the material table (for 16-bit maps, the columns gathered per neighbour) is
 // staged in LDS, so the material gathers of a cell are LDS reads rather than
 // a second dependent trip to the cache hierarchy, and the class bytes of a
 // segment's z column are read four at a time through the scalar cache, one
